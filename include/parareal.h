@@ -1,0 +1,183 @@
+/*
+ * parareal.h -- C ABI of the MI355X (gfx950) Parareal solver for the
+ * two-asset Black-Scholes equation.
+ *
+ * The method: Parareal, Eq. (parareal) of Sec. 3.1 ("Space-time parallel
+ * scaling of Parareal with a physics-informed Fourier Neural Operator coarse
+ * propagator applied to the Black-Scholes equation", Ibrahim, Goetschel,
+ * Ruprecht), applied to the two-asset Black-Scholes equation in
+ * time-to-maturity form, Eq. (bse_change_variable) of Sec. 3.2, discretised
+ * in space by the centred finite differences of Eq. (fd).  Time stepping of
+ * the fine propagator F is explicit Euler; the coarse propagator G is the same
+ * scheme on a coarser grid with injection and bilinear prolongation, or G := F
+ * for tests.
+ *
+ * Conventions shared by every entry point:
+ *  - Grids are n x n nodes on [0, s_max]^2 including both boundaries; node
+ *    (i, j) sits at S1 = i*h, S2 = j*h with h = s_max/(n-1).  A full grid is
+ *    n*n doubles, row-major, index i*n + j (j = S2 index contiguous).
+ *  - Time runs as tau = T - t from tau = 0 (the payoff) to tau = T (today).
+ *    Slice k covers [k*T/N, (k+1)*T/N].
+ *  - "Device pointer" means memory allocated on the GPU the solver was
+ *    created on (e.g. a torch CUDA/HIP tensor's data_ptr()).  "Host pointer"
+ *    means ordinary CPU memory.
+ *  - The caller owns every buffer it passes (workspace, outputs, stream);
+ *    the library never frees caller memory and allocates no device memory
+ *    of its own.  Structs passed to parareal_create are copied.
+ *  - Every call returns a pr_status; no C++ exception crosses the boundary.
+ *    parareal_last_error() gives a message for the last failing call on a
+ *    solver.  A solver is not thread-safe; distinct solvers on distinct
+ *    streams are independent.
+ *  - All GPU work is enqueued on the stream given at create time.  Calls
+ *    that return results to the host (solve, serial_fine) synchronise that
+ *    stream before returning.
+ */
+#ifndef PARAREAL_H
+#define PARAREAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PR_ABI_VERSION 1
+#define PR_MAX_SLICES 1024
+
+typedef struct pr_solver pr_solver; /* opaque */
+
+typedef enum {
+    PR_OK = 0,
+    PR_EINVAL = 1,       /* an argument is out of range or inconsistent */
+    PR_EUNSTABLE = 2,    /* the requested explicit step exceeds the stability bound */
+    PR_ENOMEM = 3,       /* the workspace is smaller than parareal_workspace_bytes() */
+    PR_EDEVICE = 4,      /* a HIP runtime call failed */
+    PR_ENOTCONV = 5,     /* max_iters reached above tolerance (result still written) */
+    PR_ENONFINITE = 6,   /* a non-finite value appeared in the iteration */
+    PR_EMODEL = 7        /* coarse model unavailable */
+} pr_status;
+
+/* Payoff at maturity (tau = 0). */
+enum { PR_PAYOFF_BASKET_CALL = 0, /* max(w1 S1 + w2 S2 - K, 0) */
+       PR_PAYOFF_EXCHANGE = 1     /* max(S1 - S2, 0) */ };
+
+/* Dirichlet data on the boundary ring at time-to-maturity tau. */
+enum { PR_BC_FORWARD_INTRINSIC = 0, /* basket: max(w1 S1 + w2 S2 - K e^{-r tau}, 0);
+                                       exchange: max(S1 - S2, 0) */
+       PR_BC_DISCOUNTED_PAYOFF = 1, /* e^{-r tau} * payoff(S1, S2) */
+       PR_BC_EXACT = 2              /* exchange: Margrabe's formula; basket with w2 = 0:
+                                       w1 * BlackScholesCall(S1; K/w1) */ };
+
+/* Coarse propagator. */
+enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilinear */
+       PR_G_FINE = 2       /* G := F (test mode: Parareal stops after one iteration) */ };
+
+/* Arithmetic of the fine and numerical coarse propagators. */
+enum { PR_FP64 = 0, /* everything in FP64 */
+       PR_FP32 = 1  /* FP32 increments over an FP64 slice base; correction and norm FP64 */ };
+
+typedef struct {
+    int32_t n;       /* nodes per side, >= 5 */
+    int32_t pad_;
+    double s_max;    /* domain [0, s_max]^2, > 0 */
+} pr_grid;
+
+typedef struct {
+    double sigma1, sigma2; /* volatilities, > 0 */
+    double rho;            /* correlation, |rho| < 1 */
+    double r;              /* risk-free rate, >= 0 */
+    double T;              /* maturity, > 0 */
+} pr_model;
+
+typedef struct {
+    int32_t kind;    /* PR_PAYOFF_* */
+    int32_t bc_kind; /* PR_BC_* */
+    double w1, w2;   /* basket weights (ignored by the exchange payoff) */
+    double strike;   /* K (ignored by the exchange payoff) */
+} pr_payoff;
+
+typedef struct {
+    int32_t n_slices;       /* N, 1..PR_MAX_SLICES */
+    int32_t max_iters;      /* cap on Parareal iterations K; 0 => N */
+    double tol;             /* stop when the max increment is below tol ... */
+    int32_t tol_relative;   /* ... (1: times max |U^k_N| over all nodes) */
+    int32_t precision;      /* PR_FP64 or PR_FP32 */
+    int32_t fine_steps;     /* explicit steps per slice; 0 => planned from cfl */
+    int32_t coarse_kind;    /* PR_G_* */
+    int32_t coarse_n;       /* coarse nodes per side; (n-1) % (coarse_n-1) == 0 */
+    int32_t coarse_steps;   /* coarse steps per slice; 0 => planned from cfl */
+    double cfl;             /* planned dt = dT / ceil(dT / (cfl * dt_stable)); (0, 1] */
+    uint32_t flags;         /* reserved, 0 */
+    int32_t pad_;
+} pr_options;
+
+typedef struct {
+    int32_t status;             /* pr_status of the call */
+    int32_t iters;              /* Parareal iterations performed (K) */
+    int32_t fine_steps;         /* explicit fine steps per slice */
+    int32_t coarse_steps;       /* coarse steps per slice */
+    double last_increment;      /* max |U^K_n - U^{K-1}_n| */
+    double scale;               /* max |U^K_N| over all nodes */
+    double increments[PR_MAX_SLICES + 1]; /* increments[k] after iteration k+1 */
+    double t_total_ms;          /* wall time of the call, host clock */
+    double t_fine_ms;           /* GPU time of the fine sweeps (HIP events) */
+    double t_chain_ms;          /* GPU time of the coarse chains */
+    double t_correct_ms;        /* GPU time of the corrections + norms */
+    int64_t fine_point_steps;   /* interior node updates performed by F */
+    int64_t fine_step_launches; /* explicit-step kernel launches */
+    double fine_step_bytes;     /* algorithmic bytes moved by those launches */
+    double t_step_kernels_ms;   /* GPU time of those launches alone (HIP events) */
+    uint64_t workspace_bytes;   /* bytes of workspace the solver uses */
+} pr_stats;
+
+/* Explicit-Euler stability bound and the planned step counts (host only, no
+ * GPU).  dt_stable = 2 / max over interior nodes of (|c| + R), where c and R
+ * are the centre and radius of the Gershgorin disc of the operator of
+ * Eq. (fd) at that node.  Writes fine and coarse steps per slice (the given
+ * counts, or the cfl plan when they are 0) and the two bounds.  Returns
+ * PR_EINVAL on bad arguments, PR_EUNSTABLE if a given step count exceeds the
+ * bound. */
+pr_status parareal_plan(const pr_grid* grid, const pr_model* model, const pr_options* opt,
+                        int32_t* fine_steps, int32_t* coarse_steps, double* dt_stable_fine,
+                        double* dt_stable_coarse);
+
+/* Bytes of device workspace a solver with these options needs (host only).
+ * Returns 0 when the arguments are invalid. */
+uint64_t parareal_workspace_bytes(const pr_grid* grid, const pr_options* opt);
+
+/* Create a solver.  device_workspace: device pointer to at least
+ * parareal_workspace_bytes() bytes, 256-byte aligned, owned by the caller and
+ * borrowed until parareal_destroy.  hip_stream: a hipStream_t (NULL = the
+ * default stream).  Validation happens before any GPU call. */
+pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_payoff* payoff,
+                          const pr_options* opt, void* device_workspace, uint64_t workspace_bytes,
+                          void* hip_stream, pr_solver** out);
+
+/* Run Parareal, Eq. (parareal), from the payoff at tau = 0 to tau = T and
+ * write U^K_N (n*n doubles, device pointer) to v_out.  Initialisation:
+ * U^0_0 = payoff, U^0_{k+1} = G(U^0_k).  Iterates until the max increment is
+ * below the tolerance, K = N (then the result equals serial F exactly) or
+ * K = max_iters (PR_ENOTCONV, result still written).  stats (host pointer,
+ * may be NULL) receives the iteration history and timings. */
+pr_status parareal_solve(pr_solver* s, double* v_out, pr_stats* stats);
+
+/* Serial fine solution: u <- F(u) for slices 0..N-1 from the payoff; writes
+ * the state at tau = T (n*n doubles, device pointer) to v_out. */
+pr_status parareal_serial_fine(pr_solver* s, double* v_out, pr_stats* stats);
+
+/* Apply one propagator over slice k to a full grid: op = PR_OP_FINE (F) or
+ * PR_OP_COARSE (G); in and out are device pointers to n*n doubles (may not
+ * alias).  The input's boundary ring is taken as g(tau_k) whatever it holds;
+ * the output's ring is g(tau_{k+1}). */
+enum { PR_OP_FINE = 0, PR_OP_COARSE = 1 };
+pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* in, double* out);
+
+pr_status parareal_destroy(pr_solver* s);
+const char* parareal_strerror(pr_status st);
+const char* parareal_last_error(const pr_solver* s);
+int32_t parareal_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARAREAL_H */

@@ -279,7 +279,7 @@ void orc_coarse(const orc_problem* pf, const orc_problem* pc, int m, double dt, 
  *                    U^{k+1}_0 = u0
  *                    U^{k+1}_{n+1} = f_n + (G(U^{k+1}_n) - G(U^k_n))   serial in n
  *   increment      : d^{k+1} = max_{n>=1} max |U^{k+1}_n - U^k_n|
- *   stop           : d < tol (tol_relative: d < tol * max_{n>=1} |U^{k+1}_n|),
+ *   stop           : d < tol (tol_relative: d < tol * max |U^{k+1}_N|),
  *                    or k+1 == N (U^N_n = F^n u0 exactly), or k+1 == max_iters.
  * The bracket is evaluated first so that identical coarse inputs cancel to an
  * exact zero.  U holds (N+1)*len doubles; on return U[n] = U^K_n.
@@ -324,6 +324,8 @@ int32_t orc_parareal(int64_t len, int32_t N, const double* u0, orc_prop_fn F, vo
             double a = fabs(Unew[e] - U[e]);
             if (!(a == a) || isinf(a)) finite = 0;
             if (a > d) d = a;
+        }
+        for (size_t e = L * N; e < L * (N + 1); ++e) {
             double s = fabs(Unew[e]);
             if (s > scale) scale = s;
         }

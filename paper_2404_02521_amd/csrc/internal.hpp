@@ -1,0 +1,73 @@
+// internal.hpp -- structures shared by the host driver and the gfx950 kernels.
+//
+// Storage layout of every fine-grid state in the workspace ("interior layout"):
+// only the (n-2) x (n-2) interior nodes are stored, row i-1 (S1 index i) at
+// offset (i-1)*pitch, column j-1 (S2 index j) contiguous, pitch a multiple of
+// 64 elements so that each 64-lane wavefront row load is aligned.  The
+// Dirichlet ring is never stored: every kernel evaluates it from its closed
+// form g(S1, S2, tau) when a stencil reaches it.  Slices follow each other at
+// slice_stride = (n-2)*pitch elements.
+#pragma once
+#include <cstdint>
+
+namespace pr {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // 4 wavefronts per workgroup
+constexpr int kChainThreads = 1024;  // one workgroup runs the whole coarse chain
+constexpr int kChainMaxPts = 16;     // interior points per chain thread => coarse n <= 129
+
+// Dirichlet data and payoff; everything in index form needs only h.
+struct Bc {
+    int payoff;   // PR_PAYOFF_*
+    int kind;     // PR_BC_*
+    double w1, w2, K;
+    double s1, s2, rho, r;
+    double h;     // grid spacing of the grid this struct describes
+};
+
+// Model coefficients in index form (h cancels): at node (i, j)
+//   alpha = a1 i^2, beta = a2 j^2, gamma = g12 i j, mu = hr i, nu = hr j.
+struct Coef {
+    double a1, a2, g12, hr, r;
+};
+
+struct Grid {
+    int n;            // nodes per side including the ring
+    int nin;          // n - 2
+    int pitch;        // stored row pitch in elements
+    long long stride; // elements per slice
+};
+
+// One explicit step (or the FP32 preparation step) over `count` slices
+// starting at `first`: slice s uses base time first_tau + s*dT.
+struct StepArgs {
+    Grid g;
+    Coef c;
+    Bc bc;
+    double dt;
+    double dT;        // slice length
+    int first;        // first slice index (absolute, for time)
+    int count;        // slices in this launch
+    int step;         // index q of the step: input at tau = T_n + q dt
+    int rows;         // rows per wavefront chunk
+    int nchunks;
+    int nstrips;
+    long long in_off, out_off;   // element offsets of slice `first` in in/out
+};
+
+// Coarse chain over slices [k0, k1) on a coarse grid of nc nodes per side.
+struct ChainArgs {
+    Grid fg;          // fine grid (interior layout)
+    int nc;           // coarse nodes per side
+    int q;            // (n - 1) / (nc - 1)
+    int k0, k1;
+    int steps;        // coarse steps per slice
+    int init;         // 1: c_{n+1} = Gc(c_n) (initial sweep); 0: correction chain
+    int fp32;         // 1: increment form with FP32 increments
+    Coef c;
+    Bc bc;            // coarse h
+    double dt, dT;
+};
+
+}  // namespace pr

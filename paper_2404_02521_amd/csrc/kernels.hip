@@ -1,0 +1,533 @@
+// kernels.hip -- gfx950 kernels of the Parareal hot path.
+//
+//  k_fine_step   : one explicit Euler step of the centred 9-point operator of
+//                  Eq. (fd) (Sec. 3.2) over a batch of time slices.  Three
+//                  modes: FP64 state (u+ = u + dt L u), FP32 increment
+//                  (d+ = d + dt (Lb + L d) over an FP64 base b), and the FP32
+//                  preparation step that evaluates Lb = L b in FP64 and writes
+//                  the first increment dt*Lb.
+//  k_coarse_chain: the serial sweep of Eq. (parareal) (Sec. 3.1) restricted
+//                  to the coarse grid, one workgroup, coarse state in LDS.
+//  k_correct     : U^{k+1}_{n+1} = F(U^k_n) + P(Gc_new - Gc_old) in FP64 over
+//                  all active slices, fused with the max-increment reduction.
+//  small kernels : payoff, prolongation of the initial sweep, pack / unpack
+//                  between full grids and the interior layout, finalise.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <type_traits>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace pr {
+
+enum { MODE_DIRECT = 0, MODE_INCR = 1, MODE_PREP = 2 };
+
+// ---------------------------------------------------------------------------
+// Fine stencil step.  Each wavefront owns a strip of 64 consecutive interior
+// columns and a chunk of `rows` consecutive rows of one slice.  It walks down
+// the rows keeping rows i-1, i, i+1 in registers: every value is loaded from
+// memory once per step (plus two halo columns), the j +- 1 neighbours come
+// from DPP wavefront shifts, and the Dirichlet ring is evaluated in place.
+// TI: input element type, TO: output element type.
+// ---------------------------------------------------------------------------
+template <int MODE, bool CHEAP, typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
+                                                      const float* __restrict__ lb,
+                                                      TO* __restrict__ out,
+                                                      float* __restrict__ out2, StepArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6);
+    const int strip = wid % a.nstrips;
+    const int t = wid / a.nstrips;
+    const int chunk = t % a.nchunks;
+    const int s = t / a.nchunks;
+    if (s >= a.count) return;
+
+    const int M = a.g.n;
+    const int P = a.g.pitch;
+    const int n = a.first + s;
+    const double Tn = n * a.dT;
+    const double tau = Tn + a.step * a.dt;
+    const double disc_tau = exp(-a.bc.r * tau);
+    const double disc_T = exp(-a.bc.r * Tn);
+    const int j0 = 1 + strip * kWave;
+    const int j = j0 + lane;
+    const int ia = 1 + chunk * a.rows;
+    const int ib = min(ia + a.rows, M - 1);
+    const TI* src = in + (long long)s * a.g.stride;
+
+    // Ring value of the stencil input at node (i, jj).
+    auto ring = [&](int i, int jj) -> TI {
+        const double x = i * a.bc.h, y = jj * a.bc.h;
+        double v = ring_value<CHEAP>(a.bc, x, y, tau, disc_tau);
+        if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, x, y, Tn, disc_T);
+        return (TI)v;
+    };
+    // Row i of the input as (left, centre, right) for this lane's column j.
+    auto load_row = [&](int i, TI& l, TI& c, TI& r) {
+        const bool ringrow = (i == 0) || (i == M - 1);
+        const TI* row = src + (long long)(i - 1) * P;
+        if (ringrow) {
+            c = (j <= M - 1) ? ring(i, j) : TI(0);
+        } else {
+            c = (j <= M - 2) ? row[j - 1] : (j == M - 1 ? ring(i, j) : TI(0));
+        }
+        TI h = TI(0);
+        const int jh = (lane == 0) ? j0 - 1 : j0 + kWave;
+        if (lane < 2) {
+            if (!ringrow && jh >= 1 && jh <= M - 2)
+                h = row[jh - 1];
+            else if (jh <= M - 1)
+                h = ring(i, jh);
+        }
+        const TI hl = bcast(h, 0), hr = bcast(h, 1);
+        l = shr1(c);
+        r = shl1(c);
+        if (lane == 0) l = hl;
+        if (lane == kWave - 1) r = hr;
+    };
+
+    using T = TI;
+    const double fj = (double)j;
+    const T bj = (T)(a.c.a2 * fj * fj);
+    const T nj = (T)(a.c.hr * fj);
+    const T gj = (T)(a.c.g12 * fj);
+    const T rr = (T)a.c.r;
+    const T dt = (T)a.dt;
+    const bool active = (j <= M - 2);
+
+    T lm, cm, rm, l0, c0, r0, lp, cp, rp;
+    load_row(ia - 1, lm, cm, rm);
+    load_row(ia, l0, c0, r0);
+    for (int i = ia; i < ib; ++i) {
+        load_row(i + 1, lp, cp, rp);
+        const long long o = (long long)(i - 1) * P + (j - 1);
+        float lbv = 0.f;
+        if (MODE == MODE_INCR && active) lbv = lb[(long long)s * a.g.stride + o];
+        const double fi = (double)i;
+        const T A = (T)(a.c.a1 * fi * fi);
+        const T Mu = (T)(a.c.hr * fi);
+        const T G = gj * (T)fi;
+        const T uxx = cp - T(2) * c0 + cm;
+        const T uyy = r0 - T(2) * c0 + l0;
+        const T uxy = rp + lm - lp - rm;
+        const T ux = cp - cm;
+        const T uy = r0 - l0;
+        const T L = A * uxx + bj * uyy + G * uxy + Mu * ux + nj * uy - rr * c0;
+        if (active) {
+            TO* dst = out + (long long)s * a.g.stride + o;
+            if (MODE == MODE_DIRECT) {
+                *dst = (TO)(c0 + dt * L);
+            } else if (MODE == MODE_INCR) {
+                *dst = (TO)(c0 + dt * ((T)lbv + L));
+            } else {  // MODE_PREP: TO = float, L evaluated in FP64
+                *dst = (TO)L;
+                out2[(long long)s * a.g.stride + o] = (float)(a.dt * (double)L);
+            }
+        }
+        lm = l0; cm = c0; rm = r0;
+        l0 = lp; c0 = cp; r0 = rp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse chain (numerical G restricted to the coarse grid).  One workgroup of
+// kChainThreads threads walks slices k0..k1-1 in order:
+//   g_n   = Gc(c_n)                    (`steps` explicit steps in LDS)
+//   d_n   = g_n - Gold_n,  Gold_n = g_n
+//   c_n+1 = R F(U^k_n) + d_n           (init: c_n+1 = g_n)
+// This is Eq. (parareal) at the coincident nodes: injection after bilinear
+// prolongation returns the coarse values unchanged, so the chain never needs
+// the fine grid except to read F at coincident nodes.
+// The stepped quantity (FP64 state, or FP32 increments over the FP64 base
+// c_n) is double-buffered in LDS; c_n and the FP32 Lb = L c_n live in global
+// memory (L2-resident).  Each thread owns one coarse column J and a segment of
+// consecutive rows, walked with a 3-row register window; row coefficients
+// come from an LDS table.
+// ---------------------------------------------------------------------------
+template <bool CHEAP, bool FP32>
+__global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
+    const double* __restrict__ Ucur, const void* __restrict__ Fold, double* __restrict__ Gold,
+    double* __restrict__ dcor, double* __restrict__ cst, float* __restrict__ lbc, ChainArgs a) {
+    using T = typename std::conditional<FP32, float, double>::type;
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const int nc = a.nc, nin = nc - 2, nn = nc * nc;
+    const int q = a.q;
+    const long long FS = a.fg.stride;
+    const int FP = a.fg.pitch;
+    const double hc = a.bc.h;
+    T* tab = reinterpret_cast<T*>(lds);                 // 3*nc row coefficients
+    T* buf0 = tab + ((3 * nc + 1) / 2) * 2;            // nc*nc
+    T* buf1 = buf0 + nn;                               // nc*nc
+    for (int I = tid; I < nc; I += kChainThreads) {
+        tab[3 * I] = (T)(a.c.a1 * I * I);
+        tab[3 * I + 1] = (T)(a.c.hr * I);
+        tab[3 * I + 2] = (T)(a.c.g12 * I);
+    }
+    // Ring nodes: thread tid < 4*(nc-1) owns ring node number tid.
+    const bool ring_thread = tid < 4 * (nc - 1);
+    int rI = 0, rJ = 0;
+    if (ring_thread) {
+        const int e = nc - 1, r = tid;
+        if (r < e) { rI = 0; rJ = r; }
+        else if (r < 2 * e) { rI = r - e; rJ = e; }
+        else if (r < 3 * e) { rI = e; rJ = e - (r - 2 * e); }
+        else { rI = e - (r - 3 * e); rJ = 0; }
+    }
+    auto gring = [&](double t) {
+        return ring_value<CHEAP>(a.bc, rI * hc, rJ * hc, t, exp(-a.bc.r * t));
+    };
+    // Column and row segment of this thread.
+    const int ncolt = (nin + kWave - 1) / kWave * kWave;
+    const int segs = kChainThreads / ncolt;
+    const int rows = (nin + segs - 1) / segs;
+    const int J = 1 + tid % ncolt;
+    const int I0 = 1 + (tid / ncolt) * rows;
+    const int nr = (J <= nin) ? max(0, min(rows, nc - 1 - I0)) : 0;
+    const T bJ = (T)(a.c.a2 * J * J), nJ = (T)(a.c.hr * J), fJ = (T)J, rr = (T)a.c.r,
+            dt = (T)a.dt;
+
+    // c_{k0} = R U_{k0}
+    for (int r = 0; r < nr; ++r)
+        cst[(I0 + r) * nc + J] =
+            Ucur[(long long)a.k0 * FS + (long long)((I0 + r) * q - 1) * FP + (J * q - 1)];
+    __syncthreads();
+
+    for (int n = a.k0; n < a.k1; ++n) {
+        const double Tn = n * a.dT;
+        const double gT = ring_thread ? gring(Tn) : 0.0;
+        int first = 0;
+        if (!FP32) {
+            for (int r = 0; r < nr; ++r) buf0[(I0 + r) * nc + J] = (T)cst[(I0 + r) * nc + J];
+            if (ring_thread) buf0[rI * nc + rJ] = (T)gT;
+        } else {
+            // Lb = L c_n in FP64 from the global c_n (ring g(T_n)); first
+            // increment dt*Lb, ring increment 0 at T_n.
+            if (ring_thread) cst[rI * nc + rJ] = gT;
+            __syncthreads();
+            for (int r = 0; r < nr; ++r) {
+                const int I = I0 + r;
+                const double* c = cst + I * nc + J;
+                const double L = a.c.a1 * I * I * (c[nc] - 2.0 * c[0] + c[-nc]) +
+                                 a.c.a2 * J * J * (c[1] - 2.0 * c[0] + c[-1]) +
+                                 a.c.g12 * I * J * (c[nc + 1] + c[-nc - 1] - c[nc - 1] - c[-nc + 1]) +
+                                 a.c.hr * I * (c[nc] - c[-nc]) + a.c.hr * J * (c[1] - c[-1]) -
+                                 a.c.r * c[0];
+                lbc[I * nc + J] = (float)L;
+                buf0[I * nc + J] = (T)(a.dt * L);
+            }
+            if (ring_thread) buf0[rI * nc + rJ] = (T)(gring(Tn + a.dt) - gT);
+            first = 1;
+        }
+        __syncthreads();
+        T* cur = buf0;
+        T* nxt = buf1;
+        for (int st = first; st < a.steps; ++st) {
+            if (nr > 0) {
+                T upl = cur[(I0 - 1) * nc + J - 1], up = cur[(I0 - 1) * nc + J],
+                  upr = cur[(I0 - 1) * nc + J + 1];
+                T cl = cur[I0 * nc + J - 1], c = cur[I0 * nc + J], cr = cur[I0 * nc + J + 1];
+                for (int r = 0; r < nr; ++r) {
+                    const int I = I0 + r;
+                    const T dnl = cur[(I + 1) * nc + J - 1], dn = cur[(I + 1) * nc + J],
+                            dnr = cur[(I + 1) * nc + J + 1];
+                    const T A = tab[3 * I], Mu = tab[3 * I + 1], G = tab[3 * I + 2] * fJ;
+                    const T L = A * (dn - T(2) * c + up) + bJ * (cr - T(2) * c + cl) +
+                                G * (dnr + upl - dnl - upr) + Mu * (dn - up) + nJ * (cr - cl) -
+                                rr * c;
+                    nxt[I * nc + J] = FP32 ? c + dt * ((T)lbc[I * nc + J] + L) : c + dt * L;
+                    upl = cl; up = c; upr = cr;
+                    cl = dnl; c = dn; cr = dnr;
+                }
+            }
+            if (ring_thread) {
+                const double t1 = Tn + (st + 1) * a.dt;
+                nxt[rI * nc + rJ] = (T)(gring(t1) - (FP32 ? gT : 0.0));
+            }
+            __syncthreads();
+            T* t = cur; cur = nxt; nxt = t;
+        }
+        // g_n = Gc(c_n) -> d_n, Gold_n and the next coarse state c_{n+1}
+        double* Go = Gold + (long long)n * nn;
+        double* dc = dcor + (long long)n * nn;
+        if (ring_thread) {
+            Go[rI * nc + rJ] = gring(Tn + a.steps * a.dt);
+            dc[rI * nc + rJ] = 0.0;
+        }
+        for (int r = 0; r < nr; ++r) {
+            const int I = I0 + r, off = I * nc + J;
+            const double g = FP32 ? cst[off] + (double)cur[off] : (double)cur[off];
+            if (a.init) {
+                Go[off] = g;
+                dc[off] = 0.0;
+                cst[off] = g;
+            } else {
+                const double d = g - Go[off];
+                Go[off] = g;
+                dc[off] = d;
+                const long long fo = (long long)n * FS + (long long)(I * q - 1) * FP + (J * q - 1);
+                const double fold = FP32 ? Ucur[fo] + (double)((const float*)Fold)[fo]
+                                         : ((const double*)Fold)[fo];
+                cst[off] = fold + d;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Correction + norm over slices n in [k0, k1):
+//   U^{k+1}_{n+1} = F_n + P(d_n)   (numerical G, d_n coarse)   or
+//   U^{k+1}_{n+1} = F_n + (g - Gf_n), Gf_n = g   (G on the fine grid, one slice)
+// with F_n = U^k_n + delta_n (FP32) or w_n (FP64), and the fused reductions
+// red[0] = max |U^{k+1} - U^k| (bit pattern), red[1] = max |U^{k+1}_N|,
+// red[2] = non-finite flag.  P is bilinear prolongation.
+// ---------------------------------------------------------------------------
+struct CorrArgs {
+    Grid g;
+    int k0, k1, N, nc, q, fp32, fineg;
+};
+
+__device__ inline void wave_max2(double& a, double& b) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmax(a, __shfl_xor(a, o));
+        b = fmax(b, __shfl_xor(b, o));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_correct(const double* __restrict__ Ucur,
+                                                    const void* __restrict__ Fold,
+                                                    const double* __restrict__ dcor,
+                                                    const double* __restrict__ gfine,
+                                                    double* __restrict__ Gf,
+                                                    double* __restrict__ Unext,
+                                                    unsigned long long* __restrict__ red,
+                                                    CorrArgs a) {
+    __shared__ double sm[2][kBlock / kWave];
+    __shared__ int sflag;
+    if (threadIdx.x == 0) sflag = 0;
+    const int nin = a.g.nin;
+    const int segs = (nin + kBlock - 1) / kBlock;
+    const int row = blockIdx.x / segs;
+    const int jj = (blockIdx.x % segs) * kBlock + threadIdx.x;   // 0-based interior column
+    const int n = a.k0 + blockIdx.y;
+    double inc = 0.0, sc = 0.0;
+    int bad = 0;
+    __syncthreads();
+    if (jj < nin) {
+        const int i = row + 1, j = jj + 1;
+        const long long o = (long long)row * a.g.pitch + jj;
+        const long long on = (long long)n * a.g.stride + o;
+        const long long on1 = (long long)(n + 1) * a.g.stride + o;
+        const double fo = a.fp32 ? Ucur[on] + (double)((const float*)Fold)[on]
+                                 : ((const double*)Fold)[on];
+        double corr;
+        if (a.fineg) {
+            const long long ol = o;   // gfine holds one slice
+            const double g = gfine[ol];
+            corr = g - Gf[on];
+            Gf[on] = g;
+        } else {
+            const int q = a.q, nc = a.nc;
+            const int I = i / q, J = j / q;
+            const double al = (double)(i - I * q) / (double)q;
+            const double be = (double)(j - J * q) / (double)q;
+            const double* d = dcor + (long long)n * nc * nc + I * nc + J;
+            corr = (1.0 - al) * (1.0 - be) * d[0] + (1.0 - al) * be * d[1] +
+                   al * (1.0 - be) * d[nc] + al * be * d[nc + 1];
+        }
+        const double v = fo + corr;
+        const double old = Ucur[on1];
+        Unext[on1] = v;
+        inc = fabs(v - old);
+        if (!(inc <= DBL_MAX)) bad = 1;
+        if (n + 1 == a.N) sc = fabs(v);
+    }
+    if (bad) sflag = 1;   // benign race: every writer stores 1
+    wave_max2(inc, sc);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sm[0][w] = inc; sm[1][w] = sc; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m0 = sm[0][0], m1 = sm[1][0];
+        for (int k = 1; k < kBlock / kWave; ++k) { m0 = fmax(m0, sm[0][k]); m1 = fmax(m1, sm[1][k]); }
+        if (m0 > 0.0) atomicMax(&red[0], (unsigned long long)__double_as_longlong(m0));
+        if (m1 > 0.0) atomicMax(&red[1], (unsigned long long)__double_as_longlong(m1));
+        if (sflag) atomicMax(&red[2], 1ull);
+    }
+}
+
+__global__ void k_zero_red(unsigned long long* red) {
+    if (threadIdx.x < 4) red[threadIdx.x] = 0ull;
+}
+
+// Interior of slice 0 <- payoff.
+__global__ void k_payoff(double* __restrict__ U, Grid g, Bc bc) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (jj >= g.nin) return;
+    U[(long long)row * g.pitch + jj] = payoff_at(bc, (row + 1) * bc.h, (jj + 1) * bc.h);
+}
+
+// U_{n+1} (interior) <- P(Gold_n) for n in [k0, k1) (initial sweep).
+__global__ void k_prolong(const double* __restrict__ Gold, double* __restrict__ U, Grid g, int nc,
+                          int q, int k0) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    const int n = k0 + blockIdx.z;
+    if (jj >= g.nin) return;
+    const int i = row + 1, j = jj + 1;
+    const int I = i / q, J = j / q;
+    const double al = (double)(i - I * q) / (double)q;
+    const double be = (double)(j - J * q) / (double)q;
+    const double* c = Gold + (long long)n * nc * nc + I * nc + J;
+    U[(long long)(n + 1) * g.stride + (long long)row * g.pitch + jj] =
+        (1.0 - al) * (1.0 - be) * c[0] + (1.0 - al) * be * c[1] + al * (1.0 - be) * c[nc] +
+        al * be * c[nc + 1];
+}
+
+// Interior layout <- full n x n grid (ring ignored).
+__global__ void k_pack(const double* __restrict__ full, double* __restrict__ U, Grid g) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (jj >= g.nin) return;
+    U[(long long)row * g.pitch + jj] = full[(long long)(row + 1) * g.n + jj + 1];
+}
+
+// Full n x n grid <- interior layout, ring = g(tau).
+__global__ void k_unpack(const double* __restrict__ U, double* __restrict__ full, Grid g, Bc bc,
+                         double tau) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= g.n) return;
+    double v;
+    if (i == 0 || i == g.n - 1 || j == 0 || j == g.n - 1)
+        v = ring_value(bc, i * bc.h, j * bc.h, tau, exp(-bc.r * tau));
+    else
+        v = U[(long long)(i - 1) * g.pitch + (j - 1)];
+    full[(long long)i * g.n + j] = v;
+}
+
+// U_out = U_in + delta (FP32 increments), interior, one slice.
+__global__ void k_finalize(const double* __restrict__ Uin, const float* __restrict__ d,
+                           double* __restrict__ Uout, Grid g) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = blockIdx.y;
+    if (jj >= g.nin) return;
+    const long long o = (long long)row * g.pitch + jj;
+    Uout[o] = Uin[o] + (double)d[o];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (C++ linkage, used by the driver).
+// ---------------------------------------------------------------------------
+static int step_waves(const StepArgs& a) { return a.count * a.nchunks * a.nstrips; }
+
+template <int MODE, typename TI, typename TO>
+static hipError_t launch_step(const TI* in, const float* lb, TO* out, float* out2,
+                              const StepArgs& a, hipStream_t st) {
+    const int blocks = (step_waves(a) + 3) / 4;
+    if (a.bc.kind == 2)
+        hipLaunchKernelGGL((k_fine_step<MODE, false, TI, TO>), dim3(blocks), dim3(kBlock), 0, st,
+                           in, lb, out, out2, a);
+    else
+        hipLaunchKernelGGL((k_fine_step<MODE, true, TI, TO>), dim3(blocks), dim3(kBlock), 0, st,
+                           in, lb, out, out2, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fine_step_f64(const double* in, double* out, const StepArgs& a, hipStream_t st) {
+    return launch_step<MODE_DIRECT, double, double>(in, nullptr, out, nullptr, a, st);
+}
+
+hipError_t launch_fine_step_f32(const float* in, const float* lb, float* out, const StepArgs& a,
+                                hipStream_t st) {
+    return launch_step<MODE_INCR, float, float>(in, lb, out, nullptr, a, st);
+}
+
+hipError_t launch_fine_prep(const double* base, float* lb, float* d1, const StepArgs& a,
+                            hipStream_t st) {
+    return launch_step<MODE_PREP, double, float>(base, nullptr, lb, d1, a, st);
+}
+
+hipError_t chain_set_lds(int bytes) {
+    const void* fns[4] = {(const void*)k_coarse_chain<true, true>, (const void*)k_coarse_chain<true, false>,
+                          (const void*)k_coarse_chain<false, true>, (const void*)k_coarse_chain<false, false>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int chain_lds_bytes(int nc, int fp32) {
+    const int es = fp32 ? 4 : 8;
+    return (((3 * nc + 1) / 2) * 2 + 2 * nc * nc) * es;
+}
+
+hipError_t launch_chain(const double* Ucur, const void* Fold, double* Gold, double* dcor,
+                        double* cst, float* lbc, const ChainArgs& a, hipStream_t st) {
+    const int lds = chain_lds_bytes(a.nc, a.fp32);
+#define PR_CHAIN(C, F)                                                                    \
+    hipLaunchKernelGGL((k_coarse_chain<C, F>), dim3(1), dim3(kChainThreads), lds, st, Ucur, Fold, \
+                       Gold, dcor, cst, lbc, a)
+    if (a.bc.kind == 2) {
+        if (a.fp32) PR_CHAIN(false, true); else PR_CHAIN(false, false);
+    } else {
+        if (a.fp32) PR_CHAIN(true, true); else PR_CHAIN(true, false);
+    }
+#undef PR_CHAIN
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const double* Ucur, const void* Fold, const double* dcor,
+                          const double* gfine, double* Gf, double* Unext,
+                          unsigned long long* red, const Grid& g, int k0, int k1, int N, int nc,
+                          int q, int fp32, int fineg, hipStream_t st) {
+    CorrArgs a{g, k0, k1, N, nc, q, fp32, fineg};
+    const int segs = (g.nin + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_correct, dim3(g.nin * segs, k1 - k0), dim3(kBlock), 0, st, Ucur, Fold,
+                       dcor, gfine, Gf, Unext, red, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_red(unsigned long long* red, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_red, dim3(1), dim3(64), 0, st, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_payoff(double* U, const Grid& g, const Bc& bc, hipStream_t st) {
+    hipLaunchKernelGGL(k_payoff, dim3((g.nin + 255) / 256, g.nin), dim3(256), 0, st, U, g, bc);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const double* Gold, double* U, const Grid& g, int nc, int q, int k0,
+                          int k1, hipStream_t st) {
+    hipLaunchKernelGGL(k_prolong, dim3((g.nin + 255) / 256, g.nin, k1 - k0), dim3(256), 0, st,
+                       Gold, U, g, nc, q, k0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const double* full, double* U, const Grid& g, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack, dim3((g.nin + 255) / 256, g.nin), dim3(256), 0, st, full, U, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const double* U, double* full, const Grid& g, const Bc& bc, double tau,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_unpack, dim3((g.n + 255) / 256, g.n), dim3(256), 0, st, U, full, g, bc,
+                       tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* Uin, const float* d, double* Uout, const Grid& g,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3((g.nin + 255) / 256, g.nin), dim3(256), 0, st, Uin, d,
+                       Uout, g);
+    return hipGetLastError();
+}
+
+}  // namespace pr

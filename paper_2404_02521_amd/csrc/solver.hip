@@ -1,0 +1,674 @@
+// solver.hip -- host driver and C ABI of the Parareal solver (include/parareal.h).
+//
+// One solve on one GPU:
+//   init   : U_0 = payoff; coarse sweep c_{n+1} = Gc(c_n); U_{n+1} = P(c_{n+1})
+//   iter k : F sweep over the active slices n = k..N-1 (all slices in one
+//            launch per explicit step), coarse chain over n = k..N-1,
+//            correction + norm over n = k..N-1, 24-byte read-back of the norms.
+// Slices n <= k are converged after iteration k (U^k_n = F^n u0) and are
+// neither propagated nor corrected again.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/parareal.h"
+#include "internal.hpp"
+
+namespace pr {
+hipError_t launch_fine_step_f64(const double*, double*, const StepArgs&, hipStream_t);
+hipError_t launch_fine_step_f32(const float*, const float*, float*, const StepArgs&, hipStream_t);
+hipError_t launch_fine_prep(const double*, float*, float*, const StepArgs&, hipStream_t);
+hipError_t chain_set_lds(int);
+hipError_t launch_chain(const double*, const void*, double*, double*, double*, float*,
+                        const ChainArgs&, hipStream_t);
+int chain_lds_bytes(int, int);
+hipError_t launch_correct(const double*, const void*, const double*, const double*, double*,
+                          double*, unsigned long long*, const Grid&, int, int, int, int, int,
+                          int, int, hipStream_t);
+hipError_t launch_zero_red(unsigned long long*, hipStream_t);
+hipError_t launch_payoff(double*, const Grid&, const Bc&, hipStream_t);
+hipError_t launch_prolong(const double*, double*, const Grid&, int, int, int, int, hipStream_t);
+hipError_t launch_pack(const double*, double*, const Grid&, hipStream_t);
+hipError_t launch_unpack(const double*, double*, const Grid&, const Bc&, double, hipStream_t);
+hipError_t launch_finalize(const double*, const float*, double*, const Grid&, hipStream_t);
+}  // namespace pr
+
+using namespace pr;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+uint64_t al(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+Grid make_grid(int n) {
+    Grid g;
+    g.n = n;
+    g.nin = n - 2;
+    g.pitch = (g.nin + kWave - 1) / kWave * kWave;
+    g.stride = (long long)g.nin * g.pitch;
+    return g;
+}
+
+// Gershgorin bound of explicit Euler for the operator of Eq. (fd) in index
+// form: row (i, j) has centre c = -(2 alpha + 2 beta + r) and radius
+// R = |alpha + mu| + |alpha - mu| + |beta + nu| + |beta - nu| + 4 |gamma|;
+// |1 + dt lambda| <= 1 for every eigenvalue when dt <= 2 / (|c| + R).
+double gershgorin_dt(int n, const pr_model& m) {
+    const double a1 = 0.5 * m.sigma1 * m.sigma1, a2 = 0.5 * m.sigma2 * m.sigma2;
+    const double g12 = 0.25 * m.rho * m.sigma1 * m.sigma2, hr = 0.5 * m.r;
+    double worst = 0.0;
+    for (int i = 1; i < n - 1; ++i) {
+        const double al_ = a1 * i * i, mu = hr * i;
+        const double rx = std::fabs(al_ + mu) + std::fabs(al_ - mu);
+        for (int j = 1; j < n - 1; ++j) {
+            const double be = a2 * j * j, nu = hr * j;
+            const double ga = g12 * i * j;
+            const double v = 2.0 * al_ + 2.0 * be + m.r + rx + std::fabs(be + nu) +
+                             std::fabs(be - nu) + 4.0 * std::fabs(ga);
+            worst = std::max(worst, v);
+        }
+    }
+    return 2.0 / worst;
+}
+
+struct Layout {
+    uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red, total;
+};
+
+bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
+    auto fail = [&](const char* m) { if (why) *why = m; return false; };
+    if (!g || !o) return fail("null argument");
+    if (g->n < 5) return fail("grid.n must be >= 5");
+    if (!(g->s_max > 0.0)) return fail("grid.s_max must be > 0");
+    if (o->n_slices < 1 || o->n_slices > PR_MAX_SLICES) return fail("n_slices out of range");
+    if (o->precision != PR_FP64 && o->precision != PR_FP32) return fail("unknown precision");
+    if (o->coarse_kind != PR_G_NUMERICAL && o->coarse_kind != PR_G_FINE)
+        return fail("unknown coarse_kind");
+    if (o->coarse_kind == PR_G_NUMERICAL) {
+        if (o->coarse_n < 3) return fail("coarse_n must be >= 3");
+        if ((g->n - 1) % (o->coarse_n - 1) != 0)
+            return fail("(n-1) must be divisible by (coarse_n-1)");
+        if (o->coarse_n > 129) return fail("coarse_n above 129 is not supported");
+        if (o->precision == PR_FP64 && o->coarse_n > 89)
+            return fail("coarse_n above 89 is not supported in FP64");
+    }
+    if (o->fine_steps < 0 || o->coarse_steps < 0) return fail("negative step count");
+    if ((o->fine_steps == 0 || o->coarse_steps == 0) && !(o->cfl > 0.0 && o->cfl <= 1.0))
+        return fail("cfl must be in (0, 1] when a step count is planned");
+    if (o->max_iters < 0) return fail("max_iters must be >= 0");
+    if (!(o->tol >= 0.0)) return fail("tol must be >= 0");
+    return true;
+}
+
+Layout layout(const pr_grid* g, const pr_options* o) {
+    const Grid fg = make_grid(g->n);
+    const uint64_t N = o->n_slices;
+    const uint64_t sd = (uint64_t)fg.stride * 8, sf = (uint64_t)fg.stride * 4;
+    const bool fp32 = o->precision == PR_FP32;
+    const bool fineg = o->coarse_kind == PR_G_FINE;
+    const uint64_t nc = fineg ? 0 : (uint64_t)o->coarse_n;
+    Layout L{};
+    uint64_t p = 0;
+    auto take = [&](uint64_t bytes) { uint64_t at = p; p = al(p + bytes); return at; };
+    L.Ua = take((N + 1) * sd);
+    L.Ub = take((N + 1) * sd);
+    L.dA = take(fp32 ? N * sf : 0);
+    L.dB = take(fp32 ? N * sf : 0);
+    L.Lb = take(fp32 ? N * sf : 0);
+    L.wA = take(fp32 ? 0 : N * sd);
+    L.wB = take(fp32 ? 0 : N * sd);
+    L.Gold = take(N * nc * nc * 8);
+    L.dcor = take(N * nc * nc * 8);
+    L.cst = take(nc * nc * 8);
+    L.lbc = take(nc * nc * 4);
+    L.Gf = take(fineg ? N * sd : 0);
+    L.tA = take(fineg && fp32 ? sf : 0);
+    L.tB = take(fineg && fp32 ? sf : 0);
+    L.tLb = take(fineg && fp32 ? sf : 0);
+    L.twA = take(fineg && !fp32 ? sd : 0);
+    L.twB = take(fineg && !fp32 ? sd : 0);
+    L.tg = take(fineg ? sd : 0);
+    L.red = take(64);
+    L.total = p;
+    return L;
+}
+
+}  // namespace
+
+struct pr_solver {
+    pr_grid grid{};
+    pr_model model{};
+    pr_payoff pay{};
+    pr_options opt{};
+    hipStream_t stream = nullptr;
+    Grid fg{};
+    Coef coef{};
+    Bc bcf{}, bcc{};
+    int N = 0, nc = 0, q = 1, mF = 0, mG = 0, maxit = 0;
+    double dT = 0, dtF = 0, dtG = 0, ring_max_T = 0;
+    bool fp32 = false, fineg = false;
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    Layout L{};
+    hipEvent_t ev[6]{};
+    bool events = false;
+    std::string err;
+
+    template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
+    double* U(int which) { return at<double>(which ? L.Ub : L.Ua); }
+    unsigned long long* red() { return at<unsigned long long>(L.red); }
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            s->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+            return PR_EDEVICE;                                                       \
+        }                                                                            \
+    } while (0)
+
+StepArgs step_args(pr_solver* s, const Grid& g, const Bc& bc, double dt, int first, int count,
+                   int step) {
+    StepArgs a{};
+    a.g = g;
+    a.c = s->coef;
+    a.bc = bc;
+    a.dt = dt;
+    a.dT = s->dT;
+    a.first = first;
+    a.count = count;
+    a.step = step;
+    a.nstrips = (g.nin + kWave - 1) / kWave;
+    // rows per wavefront: enough wavefronts to fill 256 CUs several times over
+    const long long per_slice_cols = (long long)a.nstrips * count;
+    int rows = (int)std::min<long long>(64, std::max<long long>(8, (long long)g.nin * per_slice_cols / 16384));
+    a.rows = rows;
+    a.nchunks = (g.nin + rows - 1) / rows;
+    return a;
+}
+
+// F over slices [first, first+count) from base U (interior layout, slice
+// `first` at U + first*stride).  FP32: result increments land in *dres (dA or
+// dB); FP64: the state lands in *wres.  `tmp` selects the single-slice
+// temporaries (G = F chain) instead of the per-slice buffers.
+pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bool tmp,
+                     const float** dres, const double** wres, double* step_ms) {
+    const Grid& g = s->fg;
+    const long long off = tmp ? 0 : (long long)first * g.stride;
+    if (s->fp32) {
+        float* A = s->at<float>(tmp ? s->L.tA : s->L.dA) + off;
+        float* B = s->at<float>(tmp ? s->L.tB : s->L.dB) + off;
+        float* Lb = s->at<float>(tmp ? s->L.tLb : s->L.Lb) + off;
+        StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
+        HIPCHK(launch_fine_prep(Ubase + (long long)first * g.stride, Lb, A, a, s->stream));
+        if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+        for (int q = 1; q < s->mF; ++q) {
+            a.step = q;
+            HIPCHK(launch_fine_step_f32(A, Lb, B, a, s->stream));
+            std::swap(A, B);
+        }
+        if (step_ms && s->events) {
+            HIPCHK(hipEventRecord(s->ev[5], s->stream));
+        }
+        *dres = A - off;
+    } else {
+        double* A = s->at<double>(tmp ? s->L.twA : s->L.wA) + off;
+        double* B = s->at<double>(tmp ? s->L.twB : s->L.wB) + off;
+        StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
+        if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+        HIPCHK(launch_fine_step_f64(Ubase + (long long)first * g.stride, A, a, s->stream));
+        for (int q = 1; q < s->mF; ++q) {
+            a.step = q;
+            HIPCHK(launch_fine_step_f64(A, B, a, s->stream));
+            std::swap(A, B);
+        }
+        if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[5], s->stream));
+        *wres = A - off;
+    }
+    return PR_OK;
+}
+
+// U_out (one slice) <- F result of slice `slice`.
+pr_status fine_result_to_state(pr_solver* s, const double* Ubase_slice, const float* d,
+                               const double* w, double* Uout_slice) {
+    const Grid& g = s->fg;
+    if (s->fp32)
+        HIPCHK(launch_finalize(Ubase_slice, d, Uout_slice, g, s->stream));
+    else
+        HIPCHK(hipMemcpyAsync(Uout_slice, w, (size_t)g.stride * 8, hipMemcpyDeviceToDevice,
+                              s->stream));
+    return PR_OK;
+}
+
+ChainArgs chain_args(pr_solver* s, int k0, int k1, int init) {
+    ChainArgs a{};
+    a.fg = s->fg;
+    a.nc = s->nc;
+    a.q = s->q;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.steps = s->mG;
+    a.init = init;
+    a.fp32 = s->fp32 ? 1 : 0;
+    a.c = s->coef;
+    a.bc = s->bcc;
+    a.dt = s->dtG;
+    a.dT = s->dT;
+    return a;
+}
+
+double elapsed(pr_solver* s, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[a], s->ev[b]) != hipSuccess) return 0.0;
+    return ms;
+}
+
+double host_ring_max(const pr_solver* s, double tau) {
+    // max |g| over the fine ring at tau (host evaluation of the same closed forms)
+    const Bc& b = s->bcf;
+    auto payoff = [&](double x, double y) {
+        double v = (b.payoff == 1) ? (x - y) : (b.w1 * x + b.w2 * y - b.K);
+        return v > 0 ? v : 0.0;
+    };
+    auto ncdf = [](double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); };
+    auto g = [&](double x, double y) {
+        const double disc = std::exp(-b.r * tau);
+        if (b.kind == PR_BC_DISCOUNTED_PAYOFF) return disc * payoff(x, y);
+        if (b.kind == PR_BC_EXACT) {
+            if (b.payoff == 1) {
+                if (tau <= 0) return payoff(x, y);
+                if (x <= 0) return 0.0;
+                if (y <= 0) return x;
+                double sd = std::sqrt((b.s1 * b.s1 + b.s2 * b.s2 - 2 * b.rho * b.s1 * b.s2) * tau);
+                double d1 = (std::log(x / y) + 0.5 * sd * sd) / sd;
+                return x * ncdf(d1) - y * ncdf(d1 - sd);
+            }
+            double S = x, K = b.K / b.w1;
+            if (tau <= 0) return b.w1 * std::max(S - K, 0.0);
+            if (S <= 0) return 0.0;
+            double sd = b.s1 * std::sqrt(tau);
+            double d1 = (std::log(S / K) + (b.r + 0.5 * b.s1 * b.s1) * tau) / sd;
+            return b.w1 * (S * ncdf(d1) - K * std::exp(-b.r * tau) * ncdf(d1 - sd));
+        }
+        if (b.payoff == 1) return std::max(x - y, 0.0);
+        return std::max(b.w1 * x + b.w2 * y - b.K * disc, 0.0);
+    };
+    const int n = s->fg.n;
+    double m = 0;
+    for (int k = 0; k < n; ++k) {
+        const double t = k * b.h, e = (n - 1) * b.h;
+        m = std::max({m, std::fabs(g(0, t)), std::fabs(g(e, t)), std::fabs(g(t, 0)),
+                      std::fabs(g(t, e))});
+    }
+    return m;
+}
+
+pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
+    const Grid& g = s->fg;
+    double* U = s->U(0);
+    HIPCHK(launch_payoff(U, g, s->bcf, s->stream));
+    for (int n = 0; n < s->N; ++n) {
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, U, n, 1, false, &d, &w, nullptr);
+        if (r != PR_OK) return r;
+        r = fine_result_to_state(s, U + (long long)n * g.stride,
+                                 d ? d + (long long)n * g.stride : nullptr,
+                                 w ? w + (long long)n * g.stride : nullptr,
+                                 U + (long long)(n + 1) * g.stride);
+        if (r != PR_OK) return r;
+    }
+    if (v_out) HIPCHK(launch_unpack(U + (long long)s->N * g.stride, v_out, g, s->bcf, s->N * s->dT, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (st) {
+        st->fine_point_steps = (int64_t)s->N * s->mF * g.nin * g.nin;
+        st->fine_step_launches = (int64_t)s->N * (s->fp32 ? s->mF - 1 : s->mF);
+    }
+    return PR_OK;
+}
+
+// The G = F chain for slice n: g = F(U^{k+1}_n) into tg (one slice).
+pr_status fine_g(pr_solver* s, const double* Uslice_base_all, int n, double* gout) {
+    const float* d = nullptr;
+    const double* w = nullptr;
+    pr_status r = fine_sweep(s, Uslice_base_all, n, 1, true, &d, &w, nullptr);
+    if (r != PR_OK) return r;
+    return fine_result_to_state(s, Uslice_base_all + (long long)n * s->fg.stride, d, w, gout);
+}
+
+pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
+    const Grid& g = s->fg;
+    const int N = s->N;
+    double* Ucur = s->U(0);
+    double* Unext = s->U(1);
+    double t_fine = 0, t_chain = 0, t_corr = 0, t_steps = 0, step_bytes = 0;
+    int64_t launches = 0, psteps = 0;
+    // algorithmic bytes of one explicit step per interior node: FP32 increment
+    // form reads d and Lb and writes d (12 B); FP64 reads and writes u (16 B)
+    const double bpp = s->fp32 ? 12.0 : 16.0;
+
+    // ---- initialisation: U^0_0 = payoff, U^0_{n+1} = G(U^0_n)
+    HIPCHK(launch_payoff(Ucur, g, s->bcf, s->stream));
+    HIPCHK(hipMemcpyAsync(Unext, Ucur, (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->fineg) {
+        double* Gf = s->at<double>(s->L.Gf);
+        for (int n = 0; n < N; ++n) {
+            pr_status r = fine_g(s, Ucur, n, Ucur + (long long)(n + 1) * g.stride);
+            if (r != PR_OK) return r;
+            HIPCHK(hipMemcpyAsync(Gf + (long long)n * g.stride, Ucur + (long long)(n + 1) * g.stride,
+                                  (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+        }
+    } else {
+        ChainArgs ca = chain_args(s, 0, N, 1);
+        HIPCHK(launch_chain(Ucur, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor), s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca,
+                            s->stream));
+        HIPCHK(launch_prolong(s->at<double>(s->L.Gold), Ucur, g, s->nc, s->q, 0, N, s->stream));
+    }
+
+    int K = 0;
+    pr_status status = PR_OK;
+    double inc = 0, scale = 0;
+    for (int k = 0; k < s->maxit && k < N; ++k) {
+        // ---- F sweep over active slices k..N-1
+        const float* d = nullptr;
+        const double* w = nullptr;
+        if (s->events) HIPCHK(hipEventRecord(s->ev[0], s->stream));
+        pr_status r = fine_sweep(s, Ucur, k, N - k, false, &d, &w, &t_steps);
+        if (r != PR_OK) return r;
+        const int nsteps = s->fp32 ? s->mF - 1 : s->mF;
+        launches += nsteps;
+        psteps += (int64_t)(N - k) * s->mF * g.nin * g.nin;
+        step_bytes += (double)nsteps * (N - k) * g.nin * g.nin * bpp;
+        const void* Fold = s->fp32 ? (const void*)d : (const void*)w;
+        if (s->events) HIPCHK(hipEventRecord(s->ev[1], s->stream));
+        // ---- chain + correction
+        unsigned long long* red = s->red();
+        HIPCHK(launch_zero_red(red, s->stream));
+        if (k > 0)
+            HIPCHK(hipMemcpyAsync(Unext + (long long)k * g.stride, Ucur + (long long)k * g.stride,
+                                  (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+        if (s->fineg) {
+            double* tg = s->at<double>(s->L.tg);
+            double* Gf = s->at<double>(s->L.Gf);
+            for (int n = k; n < N; ++n) {
+                r = fine_g(s, Unext, n, tg);
+                if (r != PR_OK) return r;
+                HIPCHK(launch_correct(Ucur, Fold, nullptr, tg, Gf, Unext, red, g, n, n + 1, N, 0,
+                                      1, s->fp32, 1, s->stream));
+            }
+            if (s->events) HIPCHK(hipEventRecord(s->ev[2], s->stream));
+        } else {
+            ChainArgs ca = chain_args(s, k, N, 0);
+            HIPCHK(launch_chain(Ucur, Fold, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+                                s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
+            if (s->events) HIPCHK(hipEventRecord(s->ev[2], s->stream));
+            HIPCHK(launch_correct(Ucur, Fold, s->at<double>(s->L.dcor), nullptr, nullptr, Unext,
+                                  red, g, k, N, N, s->nc, s->q, s->fp32, 0, s->stream));
+        }
+        if (s->events) HIPCHK(hipEventRecord(s->ev[3], s->stream));
+        unsigned long long hred[3];
+        HIPCHK(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        if (s->events) {
+            t_fine += elapsed(s, 0, 1);
+            t_chain += elapsed(s, 1, 2);
+            t_corr += elapsed(s, 2, 3);
+            t_steps += elapsed(s, 4, 5);
+        }
+        std::swap(Ucur, Unext);
+        std::memcpy(&inc, &hred[0], 8);
+        double scint;
+        std::memcpy(&scint, &hred[1], 8);
+        scale = std::max(scint, s->ring_max_T);
+        K = k + 1;
+        if (st && k <= PR_MAX_SLICES) st->increments[k] = inc;
+        if (hred[2]) {
+            status = PR_ENONFINITE;
+            s->err = "non-finite value in the Parareal iteration";
+            break;
+        }
+        const double thr = s->opt.tol_relative ? s->opt.tol * scale : s->opt.tol;
+        if (inc < thr || K == N) break;
+        if (K == s->maxit) {
+            status = PR_ENOTCONV;
+            s->err = "max_iters reached above tolerance";
+        }
+    }
+    if (v_out) HIPCHK(launch_unpack(Ucur + (long long)N * g.stride, v_out, g, s->bcf, N * s->dT, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (st) {
+        st->iters = K;
+        st->last_increment = inc;
+        st->scale = scale;
+        st->t_fine_ms = t_fine;
+        st->t_chain_ms = t_chain;
+        st->t_correct_ms = t_corr;
+        st->t_step_kernels_ms = t_steps;
+        st->fine_point_steps = psteps;
+        st->fine_step_launches = launches;
+        st->fine_step_bytes = step_bytes;
+    }
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t parareal_abi_version(void) { return PR_ABI_VERSION; }
+
+const char* parareal_strerror(pr_status st) {
+    switch (st) {
+        case PR_OK: return "ok";
+        case PR_EINVAL: return "invalid argument";
+        case PR_EUNSTABLE: return "explicit step above the stability bound";
+        case PR_ENOMEM: return "workspace too small";
+        case PR_EDEVICE: return "HIP runtime error";
+        case PR_ENOTCONV: return "not converged within max_iters";
+        case PR_ENONFINITE: return "non-finite value";
+        case PR_EMODEL: return "coarse model unavailable";
+    }
+    return "unknown status";
+}
+
+const char* parareal_last_error(const pr_solver* s) { return s ? s->err.c_str() : "null solver"; }
+
+pr_status parareal_plan(const pr_grid* grid, const pr_model* model, const pr_options* opt,
+                        int32_t* fine_steps, int32_t* coarse_steps, double* dt_stable_fine,
+                        double* dt_stable_coarse) {
+    if (!grid || !model || !opt) return PR_EINVAL;
+    if (!valid_basic(grid, opt, nullptr)) return PR_EINVAL;
+    if (!(model->sigma1 > 0) || !(model->sigma2 > 0) || !(std::fabs(model->rho) < 1) ||
+        !(model->r >= 0) || !(model->T > 0))
+        return PR_EINVAL;
+    const double dT = model->T / opt->n_slices;
+    const double dsf = gershgorin_dt(grid->n, *model);
+    int mf = opt->fine_steps;
+    if (mf == 0) mf = (int)std::ceil(dT / (opt->cfl * dsf));
+    int mg = 0;
+    double dsc = 0;
+    if (opt->coarse_kind == PR_G_NUMERICAL) {
+        dsc = gershgorin_dt(opt->coarse_n, *model);
+        mg = opt->coarse_steps;
+        if (mg == 0) mg = (int)std::ceil(dT / (opt->cfl * dsc));
+    }
+    if (fine_steps) *fine_steps = mf;
+    if (coarse_steps) *coarse_steps = mg;
+    if (dt_stable_fine) *dt_stable_fine = dsf;
+    if (dt_stable_coarse) *dt_stable_coarse = dsc;
+    if (dT / mf > dsf) return PR_EUNSTABLE;
+    if (opt->coarse_kind == PR_G_NUMERICAL && dT / mg > dsc) return PR_EUNSTABLE;
+    return PR_OK;
+}
+
+uint64_t parareal_workspace_bytes(const pr_grid* grid, const pr_options* opt) {
+    if (!valid_basic(grid, opt, nullptr)) return 0;
+    return layout(grid, opt).total;
+}
+
+pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_payoff* payoff,
+                          const pr_options* opt, void* device_workspace, uint64_t workspace_bytes,
+                          void* hip_stream, pr_solver** out) {
+    if (!out) return PR_EINVAL;
+    *out = nullptr;
+    if (!grid || !model || !payoff || !opt) return PR_EINVAL;
+    std::string why;
+    if (!valid_basic(grid, opt, &why)) return PR_EINVAL;
+    if (payoff->kind != PR_PAYOFF_BASKET_CALL && payoff->kind != PR_PAYOFF_EXCHANGE) return PR_EINVAL;
+    if (payoff->bc_kind < 0 || payoff->bc_kind > 2) return PR_EINVAL;
+    if (payoff->bc_kind == PR_BC_EXACT && payoff->kind == PR_PAYOFF_BASKET_CALL &&
+        !(payoff->w2 == 0.0 && payoff->w1 > 0.0 && payoff->strike > 0.0))
+        return PR_EINVAL;
+    if (!std::isfinite(payoff->w1) || !std::isfinite(payoff->w2) || !std::isfinite(payoff->strike))
+        return PR_EINVAL;
+    int32_t mf = 0, mg = 0;
+    double dsf = 0, dsc = 0;
+    pr_status pst = parareal_plan(grid, model, opt, &mf, &mg, &dsf, &dsc);
+    if (pst != PR_OK) return pst;
+    const Layout L = layout(grid, opt);
+    if (!device_workspace || workspace_bytes < L.total) return PR_ENOMEM;
+    if (reinterpret_cast<uintptr_t>(device_workspace) % kAlign) return PR_EINVAL;
+
+    pr_solver* s = new (std::nothrow) pr_solver();
+    if (!s) return PR_ENOMEM;
+    s->grid = *grid;
+    s->model = *model;
+    s->pay = *payoff;
+    s->opt = *opt;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    s->fg = make_grid(grid->n);
+    s->N = opt->n_slices;
+    s->maxit = opt->max_iters > 0 ? std::min(opt->max_iters, s->N) : s->N;
+    s->fp32 = opt->precision == PR_FP32;
+    s->fineg = opt->coarse_kind == PR_G_FINE;
+    s->nc = s->fineg ? 0 : opt->coarse_n;
+    s->q = s->fineg ? 1 : (grid->n - 1) / (opt->coarse_n - 1);
+    s->mF = mf;
+    s->mG = mg;
+    s->dT = model->T / s->N;
+    s->dtF = s->dT / mf;
+    s->dtG = mg ? s->dT / mg : 0.0;
+    s->coef = Coef{0.5 * model->sigma1 * model->sigma1, 0.5 * model->sigma2 * model->sigma2,
+                   0.25 * model->rho * model->sigma1 * model->sigma2, 0.5 * model->r, model->r};
+    Bc b{};
+    b.payoff = payoff->kind;
+    b.kind = payoff->bc_kind;
+    b.w1 = payoff->w1;
+    b.w2 = payoff->w2;
+    b.K = payoff->strike;
+    b.s1 = model->sigma1;
+    b.s2 = model->sigma2;
+    b.rho = model->rho;
+    b.r = model->r;
+    b.h = grid->s_max / (grid->n - 1);
+    s->bcf = b;
+    b.h = s->fineg ? b.h : grid->s_max / (opt->coarse_n - 1);
+    s->bcc = b;
+    s->ws = reinterpret_cast<char*>(device_workspace);
+    s->ws_bytes = workspace_bytes;
+    s->L = L;
+    s->ring_max_T = host_ring_max(s, model->T);
+    if (!s->fineg) {
+        hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));
+        if (e != hipSuccess) {
+            delete s;
+            return PR_EDEVICE;
+        }
+    }
+    bool ok = true;
+    for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    s->events = ok;
+    *out = s;
+    return PR_OK;
+}
+
+pr_status parareal_solve(pr_solver* s, double* v_out, pr_stats* st) {
+    if (!s || !v_out) return PR_EINVAL;
+    if (st) std::memset(st, 0, sizeof(*st));
+    auto t0 = std::chrono::steady_clock::now();
+    pr_status r;
+    try {
+        r = do_solve(s, v_out, st);
+    } catch (...) {
+        s->err = "internal error";
+        r = PR_EDEVICE;
+    }
+    if (st) {
+        st->status = r;
+        st->fine_steps = s->mF;
+        st->coarse_steps = s->mG;
+        st->workspace_bytes = s->L.total;
+        st->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return r;
+}
+
+pr_status parareal_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
+    if (!s || !v_out) return PR_EINVAL;
+    if (st) std::memset(st, 0, sizeof(*st));
+    auto t0 = std::chrono::steady_clock::now();
+    pr_status r;
+    try {
+        r = do_serial_fine(s, v_out, st);
+    } catch (...) {
+        s->err = "internal error";
+        r = PR_EDEVICE;
+    }
+    if (st) {
+        st->status = r;
+        st->fine_steps = s->mF;
+        st->coarse_steps = s->mG;
+        st->iters = 0;
+        st->workspace_bytes = s->L.total;
+        st->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return r;
+}
+
+pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* in, double* out) {
+    if (!s || !in || !out || in == out) return PR_EINVAL;
+    if (slice < 0 || slice >= s->N || (op != PR_OP_FINE && op != PR_OP_COARSE)) return PR_EINVAL;
+    const Grid& g = s->fg;
+    double* U = s->U(0);
+    double* Us = U + (long long)slice * g.stride;
+    double* Us1 = U + (long long)(slice + 1) * g.stride;
+    HIPCHK(launch_pack(in, Us, g, s->stream));
+    if (op == PR_OP_FINE || s->fineg) {
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, U, slice, 1, false, &d, &w, nullptr);
+        if (r != PR_OK) return r;
+        r = fine_result_to_state(s, Us, d ? d + (long long)slice * g.stride : nullptr,
+                                 w ? w + (long long)slice * g.stride : nullptr, Us1);
+        if (r != PR_OK) return r;
+    } else {
+        ChainArgs ca = chain_args(s, slice, slice + 1, 1);
+        HIPCHK(launch_chain(U, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor), s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca,
+                            s->stream));
+        HIPCHK(launch_prolong(s->at<double>(s->L.Gold), U, g, s->nc, s->q, slice, slice + 1,
+                              s->stream));
+    }
+    HIPCHK(launch_unpack(Us1, out, g, s->bcf, (slice + 1) * s->dT, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PR_OK;
+}
+
+pr_status parareal_destroy(pr_solver* s) {
+    if (!s) return PR_EINVAL;
+    for (auto& e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete s;
+    return PR_OK;
+}
+
+}  // extern "C"

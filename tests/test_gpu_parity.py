@@ -1,0 +1,215 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: FP64 runs within 1e-10 absolute of the oracle; FP32 runs (FP32
+increments over an FP64 base, FP64 correction and norm) within 1e-5 relative
+max-norm of the FP64 oracle.  Bitwise properties (finite termination, G = F,
+determinism) compare the GPU with itself.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import abs_max, oproblem, rel_max, say
+from synthetic import BASKET, EXCHANGE, plain_at_scale, plain_fp64
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2404_02521_amd as pr_
+    return pr_
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+# ---------------------------------------------------------------- fine propagator
+@pytest.mark.parametrize("payoff", [BASKET, EXCHANGE])
+def test_c1_serial_fine_fp64(pr, payoff):
+    inst = plain_fp64(payoff)
+    say("c1 serial F fp64", payoff)
+    s = pr.Solver(inst)
+    gpu = host(s.serial_fine().value)
+    ref = oracle.serial_fine(oproblem(inst), inst.n_slices, inst.T, inst.fine_steps_per_slice)
+    assert abs_max(gpu, ref) <= FP64_TOL
+
+
+def test_apply_fine_and_coarse_fp64(pr):
+    inst = plain_fp64(BASKET)
+    pf, pc = oproblem(inst), oproblem(inst, inst.coarse_M)
+    dT = inst.T / inst.n_slices
+    u = oracle.payoff_grid(pf)
+    for n in range(3):
+        u = oracle.fine(pf, 128, dT / 128, n * dT, u)
+    say("apply F/G fp64 slice 3")
+    s = pr.Solver(inst)
+    f_gpu = host(s.apply(pr.PR_OP_FINE, 3, to_dev(u)))
+    g_gpu = host(s.apply(pr.PR_OP_COARSE, 3, to_dev(u)))
+    f_ref = oracle.fine(pf, 128, dT / 128, 3 * dT, u)
+    g_ref = oracle.coarse(pf, pc, 64, dT / 64, 3 * dT, u)
+    assert abs_max(f_gpu, f_ref) <= 1e-12
+    assert abs_max(g_gpu, g_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("M,Mc,mF,mG,N", [(5, 3, 4, 2, 2), (67, 23, 160, 24, 3),
+                                          (97, 33, 300, 40, 2), (131, 27, 600, 30, 2)])
+def test_ragged_grids_fp64(pr, M, Mc, mF, mG, N):
+    """Grids that are not 2^k + 1: partial wavefront strips and row chunks."""
+    inst = plain_fp64(BASKET).replace(M=M, coarse_M=Mc, fine_steps_per_slice=mF,
+                                      coarse_steps_per_slice=mG, n_slices=N, sigma2=0.25,
+                                      rho=-0.4)
+    say("ragged fp64", M, Mc)
+    s = pr.Solver(inst)
+    ser = host(s.serial_fine().value)
+    assert abs_max(ser, oracle.serial_fine(oproblem(inst), N, inst.T, mF)) <= FP64_TOL
+    res = s.solve()
+    U, K, _ = oracle.parareal_bs(oproblem(inst), oproblem(inst, Mc), N, inst.T, mF, mG,
+                                 tol=inst.tol)
+    assert res.iters == K
+    assert abs_max(host(res.value), U) <= FP64_TOL
+
+
+def test_exact_bc_fp64(pr):
+    """Margrabe ring (exchange) through the closed-form ring path."""
+    inst = plain_fp64(EXCHANGE)
+    say("exact bc fp64")
+    s = pr.Solver(inst, bc_kind=pr.PR_BC_EXACT)
+    gpu = host(s.serial_fine().value)
+    ref = oracle.serial_fine(oproblem(inst, bc_kind=oracle.BC_EXACT), 8, 1.0, 128)
+    assert abs_max(gpu, ref) <= FP64_TOL
+
+
+# ---------------------------------------------------------------- Parareal, FP64
+@pytest.mark.parametrize("payoff", [BASKET, EXCHANGE])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_c1_parareal_iterates_fp64(pr, payoff, k):
+    inst = plain_fp64(payoff).replace(tol=0.0)
+    say("c1 parareal fp64", payoff, k)
+    s = pr.Solver(inst, max_iters=k)
+    res = s.solve()
+    U, K, inc = oracle.parareal_bs(oproblem(inst), oproblem(inst, inst.coarse_M), 8, 1.0, 128,
+                                   64, max_iters=k, tol=0.0)
+    assert res.iters == K == k
+    assert abs_max(host(res.value), U) <= FP64_TOL
+    assert np.allclose(res.increments, inc, rtol=1e-8, atol=1e-13)
+
+
+@pytest.mark.parametrize("payoff", [BASKET, EXCHANGE])
+def test_c1_parareal_full_fp64(pr, payoff):
+    inst = plain_fp64(payoff)
+    say("c1 parareal full fp64", payoff)
+    s = pr.Solver(inst)
+    res = s.solve()
+    ser = host(s.serial_fine().value)
+    U, K, _ = oracle.parareal_bs(oproblem(inst), oproblem(inst, inst.coarse_M), 8, 1.0, 128, 64,
+                                 tol=inst.tol)
+    assert res.iters == K
+    assert abs_max(host(res.value), U) <= FP64_TOL
+    if K == inst.n_slices:
+        assert np.array_equal(host(res.value), ser)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_finite_termination_bitwise(pr, fp32):
+    inst = plain_fp64(BASKET).replace(tol=0.0, fp32=fp32)
+    say("finite termination", fp32)
+    s = pr.Solver(inst)
+    res = s.solve()
+    assert res.iters == inst.n_slices
+    assert np.array_equal(host(res.value), host(s.serial_fine().value))
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_G_equal_F_one_iteration(pr, fp32):
+    inst = plain_fp64(EXCHANGE).replace(fp32=fp32)
+    say("G=F", fp32)
+    s = pr.Solver(inst, coarse_kind=pr.PR_G_FINE)
+    res = s.solve()
+    assert res.iters == 1 and res.increments[0] == 0.0
+    assert np.array_equal(host(res.value), host(s.serial_fine().value))
+
+
+def test_single_slice(pr):
+    inst = plain_fp64(BASKET).replace(n_slices=1, fine_steps_per_slice=1024,
+                                      coarse_steps_per_slice=512)
+    say("N=1")
+    s = pr.Solver(inst)
+    res = s.solve()
+    assert res.iters == 1
+    assert np.array_equal(host(res.value), host(s.serial_fine().value))
+
+
+def test_deterministic(pr):
+    inst = plain_at_scale(3, M=129, n_slices=16, coarse_M=33)
+    say("determinism")
+    s = pr.Solver(inst, max_iters=3)
+    a = host(s.solve().value)
+    b = host(s.solve().value)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- FP32 increments
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fp32_serial_fine_vs_oracle(pr, seed):
+    inst = plain_at_scale(seed, M=129, n_slices=8, coarse_M=33)
+    mf, mg, _, _ = pr.plan(inst)
+    say("fp32 serial F 129", seed, mf)
+    s = pr.Solver(inst)
+    gpu = host(s.serial_fine().value)
+    ref = oracle.serial_fine(oproblem(inst), 8, inst.T, mf)
+    assert rel_max(gpu, ref) <= FP32_TOL
+
+
+@pytest.mark.parametrize("seed", [0, 4])
+def test_fp32_parareal_vs_oracle(pr, seed):
+    inst = plain_at_scale(seed, M=129, n_slices=8, coarse_M=33).replace(tol=0.0)
+    mf, mg, _, _ = pr.plan(inst)
+    say("fp32 parareal 129", seed)
+    for k in (1, 3):
+        s = pr.Solver(inst, max_iters=k)
+        res = s.solve()
+        U, K, inc = oracle.parareal_bs(oproblem(inst), oproblem(inst, 33), 8, inst.T, mf, mg,
+                                       max_iters=k, tol=0.0)
+        assert res.iters == K == k
+        assert rel_max(host(res.value), U) <= FP32_TOL
+        assert np.allclose(res.increments, inc, rtol=1e-3)
+
+
+def test_full_size_fine_slice_vs_oracle(pr):
+    """513^2 at the at-scale launch shape: F over slice 0 (planned steps) and G over
+    slice 0 (129^2 coarse grid), checked against the oracle."""
+    inst = plain_at_scale(0)
+    mf, mg, _, _ = pr.plan(inst)
+    pf, pc = oproblem(inst), oproblem(inst, inst.coarse_M)
+    dT = inst.T / inst.n_slices
+    u0 = oracle.payoff_grid(pf)
+    say("full-size F/G slice 0", mf, mg)
+    s = pr.Solver(inst)
+    f_gpu = host(s.apply(pr.PR_OP_FINE, 0, to_dev(u0)))
+    g_gpu = host(s.apply(pr.PR_OP_COARSE, 0, to_dev(u0)))
+    assert rel_max(f_gpu, oracle.fine(pf, mf, dT / mf, 0.0, u0)) <= FP32_TOL
+    assert rel_max(g_gpu, oracle.coarse(pf, pc, mg, dT / mg, 0.0, u0)) <= FP32_TOL
+
+
+def test_full_size_parareal_error_vs_serial(pr):
+    """At-scale solve: the returned error against serial F is what the stop rule allows."""
+    inst = plain_at_scale(3)
+    say("full-size parareal seed 3")
+    s = pr.Solver(inst)
+    res = s.solve()
+    ser = host(s.serial_fine().value)
+    err = rel_max(host(res.value), ser)
+    assert res.iters >= 1
+    assert err <= FP32_TOL, (res.iters, err)
