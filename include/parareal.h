@@ -72,6 +72,12 @@ enum { PR_BC_FORWARD_INTRINSIC = 0, /* basket: max(w1 S1 + w2 S2 - K e^{-r tau},
 enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilinear */
        PR_G_FINE = 2       /* G := F (test mode: Parareal stops after one iteration) */ };
 
+/* Option flags.  PR_FLAG_TIME_STEPS: bracket every explicit fine-step launch
+ * with HIP events on the solver's stream and report their summed durations in
+ * pr_stats.t_step_kernels_ms (otherwise the field brackets the whole run of
+ * step launches, gaps included). */
+#define PR_FLAG_TIME_STEPS 1u
+
 /* Arithmetic of the fine and numerical coarse propagators. */
 enum { PR_FP64 = 0, /* everything in FP64 */
        PR_FP32 = 1  /* FP32 increments over an FP64 slice base; correction and norm FP64 */ };
@@ -107,7 +113,7 @@ typedef struct {
     int32_t coarse_n;       /* coarse nodes per side; (n-1) % (coarse_n-1) == 0 */
     int32_t coarse_steps;   /* coarse steps per slice; 0 => planned from cfl */
     double cfl;             /* planned dt = dT / ceil(dT / (cfl * dt_stable)); (0, 1] */
-    uint32_t flags;         /* reserved, 0 */
+    uint32_t flags;         /* PR_FLAG_* bits */
     int32_t pad_;
 } pr_options;
 
@@ -126,7 +132,7 @@ typedef struct {
     int64_t fine_point_steps;   /* interior node updates performed by F */
     int64_t fine_step_launches; /* explicit-step kernel launches */
     double fine_step_bytes;     /* algorithmic bytes moved by those launches */
-    double t_step_kernels_ms;   /* GPU time of those launches alone (HIP events) */
+    double t_step_kernels_ms;   /* GPU time of those launches (HIP events, see PR_FLAG_TIME_STEPS) */
     uint64_t workspace_bytes;   /* bytes of workspace the solver uses */
 } pr_stats;
 

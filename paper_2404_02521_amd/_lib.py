@@ -20,6 +20,7 @@ PR_BC_FORWARD_INTRINSIC, PR_BC_DISCOUNTED_PAYOFF, PR_BC_EXACT = 0, 1, 2
 PR_G_NUMERICAL, PR_G_FINE = 0, 2
 PR_FP64, PR_FP32 = 0, 1
 PR_OP_FINE, PR_OP_COARSE = 0, 1
+PR_FLAG_TIME_STEPS = 1
 
 
 class pr_grid(C.Structure):

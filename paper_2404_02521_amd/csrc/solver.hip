@@ -12,9 +12,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/parareal.h"
 #include "internal.hpp"
@@ -157,6 +159,9 @@ struct pr_solver {
     Layout L{};
     hipEvent_t ev[6]{};
     bool events = false;
+    std::vector<hipEvent_t> step_ev;   // PR_FLAG_TIME_STEPS: a pair per step launch
+    int step_ev_used = 0;
+    int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
     std::string err;
 
     template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -190,6 +195,7 @@ StepArgs step_args(pr_solver* s, const Grid& g, const Bc& bc, double dt, int fir
     // rows per wavefront: enough wavefronts to fill 256 CUs several times over
     const long long per_slice_cols = (long long)a.nstrips * count;
     int rows = (int)std::min<long long>(64, std::max<long long>(8, (long long)g.nin * per_slice_cols / 16384));
+    if (s->rows_override > 0) rows = std::min(s->rows_override, g.nin);
     a.rows = rows;
     a.nchunks = (g.nin + rows - 1) / rows;
     return a;
@@ -212,7 +218,13 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
         for (int q = 1; q < s->mF; ++q) {
             a.step = q;
+            const bool tv = step_ms && s->step_ev_used + 2 <= (int)s->step_ev.size();
+            if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
             HIPCHK(launch_fine_step_f32(A, Lb, B, a, s->stream));
+            if (tv) {
+                HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
+                s->step_ev_used += 2;
+            }
             std::swap(A, B);
         }
         if (step_ms && s->events) {
@@ -224,11 +236,17 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         double* B = s->at<double>(tmp ? s->L.twB : s->L.wB) + off;
         StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
-        HIPCHK(launch_fine_step_f64(Ubase + (long long)first * g.stride, A, a, s->stream));
-        for (int q = 1; q < s->mF; ++q) {
+        for (int q = 0; q < s->mF; ++q) {
             a.step = q;
-            HIPCHK(launch_fine_step_f64(A, B, a, s->stream));
-            std::swap(A, B);
+            const bool tv = step_ms && s->step_ev_used + 2 <= (int)s->step_ev.size();
+            if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
+            HIPCHK(launch_fine_step_f64(q == 0 ? Ubase + (long long)first * g.stride : A, q == 0 ? A : B,
+                                        a, s->stream));
+            if (tv) {
+                HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
+                s->step_ev_used += 2;
+            }
+            if (q > 0) std::swap(A, B);
         }
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[5], s->stream));
         *wres = A - off;
@@ -421,8 +439,13 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
             t_fine += elapsed(s, 0, 1);
             t_chain += elapsed(s, 1, 2);
             t_corr += elapsed(s, 2, 3);
-            t_steps += elapsed(s, 4, 5);
+            if (s->step_ev.empty()) t_steps += elapsed(s, 4, 5);
         }
+        for (int e = 0; e + 1 < s->step_ev_used; e += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->step_ev[e], s->step_ev[e + 1]) == hipSuccess) t_steps += ms;
+        }
+        s->step_ev_used = 0;
         std::swap(Ucur, Unext);
         std::memcpy(&inc, &hred[0], 8);
         double scint;
@@ -576,6 +599,7 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     s->ws_bytes = workspace_bytes;
     s->L = L;
     s->ring_max_T = host_ring_max(s, model->T);
+    if (const char* e = std::getenv("PR_STEP_ROWS")) s->rows_override = std::atoi(e);
     if (!s->fineg) {
         hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));
         if (e != hipSuccess) {
@@ -586,6 +610,19 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     s->events = ok;
+    if (opt->flags & PR_FLAG_TIME_STEPS) {
+        s->step_ev.resize(2 * (size_t)mf, nullptr);
+        for (auto& e : s->step_ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                e = nullptr;
+                ok = false;
+            }
+        if (!ok) {
+            for (auto& e : s->step_ev)
+                if (e) (void)hipEventDestroy(e);
+            s->step_ev.clear();
+        }
+    }
     *out = s;
     return PR_OK;
 }
@@ -666,6 +703,8 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
 pr_status parareal_destroy(pr_solver* s) {
     if (!s) return PR_EINVAL;
     for (auto& e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : s->step_ev)
         if (e) (void)hipEventDestroy(e);
     delete s;
     return PR_OK;

@@ -31,7 +31,7 @@ def _stats_dict(st: L.pr_stats) -> dict:
 
 
 def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
-                 bc_kind: int = L.PR_BC_FORWARD_INTRINSIC):
+                 bc_kind: int = L.PR_BC_FORWARD_INTRINSIC, flags: int = 0):
     """pr_grid / pr_model / pr_payoff / pr_options from a synthetic.Instance."""
     g = L.pr_grid(inst.M, 0, inst.s_max)
     m = L.pr_model(inst.sigma1, inst.sigma2, inst.rho, inst.r, inst.T)
@@ -41,7 +41,7 @@ def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
                      precision=L.PR_FP32 if inst.fp32 else L.PR_FP64,
                      fine_steps=inst.fine_steps_per_slice, coarse_kind=coarse_kind,
                      coarse_n=inst.coarse_M, coarse_steps=inst.coarse_steps_per_slice,
-                     cfl=inst.cfl, flags=0, pad_=0)
+                     cfl=inst.cfl, flags=flags, pad_=0)
     return g, m, p, o
 
 
@@ -60,11 +60,12 @@ class Solver:
     """One solver bound to a workspace tensor and the current stream."""
 
     def __init__(self, inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
-                 bc_kind: int = L.PR_BC_FORWARD_INTRINSIC, device=None, stream=None):
+                 bc_kind: int = L.PR_BC_FORWARD_INTRINSIC, device=None, stream=None,
+                 flags: int = 0):
         import torch
         self.inst = inst
         self.device = torch.device(device or "cuda")
-        self._structs = make_structs(inst, coarse_kind, max_iters, bc_kind)
+        self._structs = make_structs(inst, coarse_kind, max_iters, bc_kind, flags)
         g, m, p, o = self._structs
         nbytes = L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o))
         if nbytes == 0:
