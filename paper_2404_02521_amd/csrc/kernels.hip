@@ -133,6 +133,187 @@ __global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
 }
 
 // ---------------------------------------------------------------------------
+// Temporally blocked fine steps: S explicit steps of the same operator per
+// launch, the intermediate time levels kept in registers.
+//
+// A wavefront owns 64 consecutive columns jl = j0 - S + lane and walks rows
+// top to bottom.  Level 0 is the input state; level q (1..S) is the state
+// after q steps.  When level-0 row x arrives, level q computes its row x - q
+// from the three newest rows of level q-1, so one pass over the rows advances
+// every level.  DPP shifts supply the j +- 1 neighbours; lane 0 / lane 63 have
+// no outer neighbour, so level q is valid on lanes [q, 63-q] and the output
+// columns are the middle W = 64 - 2S lanes.  Row chunks overlap by S rows on
+// each side for the same reason.  Each input element is read once and each
+// output element written once per S steps.  The Dirichlet ring of every level
+// is evaluated in place at that level's time.
+// MODE_INCR: FP32 increments d over an FP64 base (d+ = d + dt (Lb + L d));
+// MODE_DIRECT: FP64 state (u+ = u + dt L u).
+// ---------------------------------------------------------------------------
+template <int MODE, bool CHEAP, typename T, int S>
+__global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
+                                                    const float* __restrict__ lb,
+                                                    T* __restrict__ out, StepArgs a) {
+    constexpr int W = kWave - 2 * S;
+    const int lane = threadIdx.x & 63;
+    const int wid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6);
+    const int strip = wid % a.nstrips;
+    const int t = wid / a.nstrips;
+    const int chunk = t % a.nchunks;
+    const int s = t / a.nchunks;
+    if (s >= a.count) return;
+
+    const int M = a.g.n;
+    const int P = a.g.pitch;
+    const int n = a.first + s;
+    const double Tn = n * a.dT;
+    const double disc_T = exp(-a.bc.r * Tn);
+    const int j0 = 1 + strip * W;
+    const int jl = j0 - S + lane;
+    const bool in_col = (jl >= 1) && (jl <= M - 2);
+    const bool ring_col = (jl == 0) || (jl == M - 1);
+    const bool out_lane = (lane >= S) && (lane < S + W) && in_col;
+    // no lane of this wavefront sits on or beyond the ring columns
+    const bool strip_inner = (j0 - S >= 1) && (j0 - S + kWave - 1 <= M - 2);
+    const int ia = 1 + chunk * a.rows;
+    const int ib = min(ia + a.rows, M - 1);
+    const T* src = in + (long long)s * a.g.stride;
+    const float* lbs = lb + (long long)s * a.g.stride;
+    T* dst = out + (long long)s * a.g.stride;
+
+    double tau[S + 1], disc[S + 1];
+#pragma unroll
+    for (int q = 0; q <= S; ++q) {
+        tau[q] = Tn + (a.step + q) * a.dt;
+        disc[q] = exp(-a.bc.r * tau[q]);
+    }
+    auto ring = [&](int i, int q) __attribute__((always_inline)) -> T {
+        const double x = i * a.bc.h, y = jl * a.bc.h;
+        double v = ring_value<CHEAP>(a.bc, x, y, tau[q], disc[q]);
+        if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, x, y, Tn, disc_T);
+        return (T)v;
+    };
+
+    const T fj = (T)jl;
+    const T a1 = (T)a.c.a1, hr = (T)a.c.hr;
+    const T bj = (T)a.c.a2 * fj * fj;
+    const T nj = hr * fj;
+    const T gj = (T)a.c.g12 * fj;
+    const T rr = (T)a.c.r;
+    const T dt = (T)a.dt;
+
+    // Window of level q (0..S-1): three rows as (l, c, r) in slots 0..2; with
+    // the row loop unrolled by 3 the newest row of iteration x sits in slot
+    // x % 3, so rotating the window costs no moves.
+    T wl[S][3], wc[S][3], wr[S][3];
+    float lbw[S];   // Lb rows x-1 .. x-S (lbw[q-1] -> row x-q)
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        lbw[q] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { wl[q][k] = T(0); wc[q][k] = T(0); wr[q][k] = T(0); }
+    }
+
+    const int x0 = max(0, ia - S);
+    const int x1 = ib - 1 + S;   // last iteration (level S row ib-1)
+    // Prefetch queue: raw loads of rows x..x+2 and Lb rows x-1..x+1 in flight.
+    auto raw = [&](int x) -> T {
+        return (x >= 1 && x <= M - 2 && in_col) ? src[(long long)(x - 1) * P + (jl - 1)] : T(0);
+    };
+    auto rawlb = [&](int rl) -> float {
+        return (MODE == MODE_INCR && rl >= 1 && rl <= M - 2 && in_col)
+                   ? lbs[(long long)(rl - 1) * P + (jl - 1)]
+                   : 0.f;
+    };
+    T pq[3];
+    float lq[3];
+    // slot of row x is x % 3
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int xr = x0 + ((k - x0 % 3) + 3) % 3;   // the row in [x0, x0+2] with xr % 3 == k
+        pq[k] = raw(xr);
+        lq[k] = rawlb(xr - 1);
+    }
+
+    // One row iteration; the newest window slot is x % 3 = K (compile time).
+    // FAST (compile time): every row touched (x-S .. x) is interior and no lane
+    // is on the ring, so no boundary logic is compiled in.
+    auto iter = [&](auto Kc, auto Fc, int x) __attribute__((always_inline)) {
+        constexpr int K = decltype(Kc)::value;
+        constexpr bool FAST = decltype(Fc)::value;
+        constexpr int K1 = (K + 2) % 3;   // previous row
+        constexpr int K2 = (K + 1) % 3;   // row before that
+        const T cur_raw = pq[K];
+        const float cur_lb = lq[K];
+        pq[K] = raw(x + 3);
+        lq[K] = rawlb(x + 2);
+        if (MODE == MODE_INCR) {
+#pragma unroll
+            for (int q = S - 1; q > 0; --q) lbw[q] = lbw[q - 1];
+            lbw[0] = cur_lb;
+        }
+        {
+            T c = cur_raw;
+            if (!FAST) {
+                c = T(0);
+                if (x <= M - 1) {
+                    if (x == 0 || x == M - 1 || ring_col)
+                        c = (jl >= 0 && jl <= M - 1) ? ring(x, 0) : T(0);
+                    else
+                        c = cur_raw;
+                }
+            }
+            wl[0][K] = shr1(c); wc[0][K] = c; wr[0][K] = shl1(c);
+        }
+#pragma unroll
+        for (int q = 1; q <= S; ++q) {
+            const int row = x - q;
+            const T um = wc[q - 1][K2], u0 = wc[q - 1][K1], up = wc[q - 1][K];
+            const T lm = wl[q - 1][K2], l0 = wl[q - 1][K1], lp = wl[q - 1][K];
+            const T rm = wr[q - 1][K2], r0 = wr[q - 1][K1], rp = wr[q - 1][K];
+            const T fi = (T)row;
+            const T A = a1 * fi * fi, Mu = hr * fi, G = gj * fi;
+            const T L = A * (up - T(2) * u0 + um) + bj * (r0 - T(2) * u0 + l0) +
+                        G * (rp + lm - lp - rm) + Mu * (up - um) + nj * (r0 - l0) - rr * u0;
+            T c = (MODE == MODE_INCR) ? u0 + dt * ((T)lbw[q - 1] + L) : u0 + dt * L;
+            if (!FAST) {
+                if (row < 0 || row > M - 1)
+                    c = T(0);
+                else if (row == 0 || row == M - 1 || ring_col)
+                    c = (jl >= 0 && jl <= M - 1) ? ring(row, q) : T(0);
+            }
+            if (q == S) {
+                if (row >= ia && row < ib && out_lane) dst[(long long)(row - 1) * P + (jl - 1)] = c;
+            } else {
+                wl[q][K] = shr1(c); wc[q][K] = c; wr[q][K] = shl1(c);
+            }
+        }
+    };
+    using F0 = std::integral_constant<bool, false>;
+    using F1 = std::integral_constant<bool, true>;
+    using C0 = std::integral_constant<int, 0>;
+    using C1 = std::integral_constant<int, 1>;
+    using C2 = std::integral_constant<int, 2>;
+    auto general = [&](int x) __attribute__((always_inline)) {
+        switch (x % 3) {
+            case 0: iter(C0{}, F0{}, x); break;
+            case 1: iter(C1{}, F0{}, x); break;
+            default: iter(C2{}, F0{}, x); break;
+        }
+    };
+    // interior iterations: x in [S+1, M-2] for strips away from the ring columns
+    const int fb = strip_inner ? max(x0, S + 1) : x1 + 1;
+    const int fe = strip_inner ? min(x1, M - 2) : x1;
+    int x = x0;
+    while (x <= x1 && (x < fb || x % 3 != 0)) general(x++);
+    for (; x + 2 <= fe; x += 3) {
+        iter(C0{}, F1{}, x);
+        iter(C1{}, F1{}, x + 1);
+        iter(C2{}, F1{}, x + 2);
+    }
+    while (x <= x1) general(x++);
+}
+
+// ---------------------------------------------------------------------------
 // Coarse chain (numerical G restricted to the coarse grid).  One workgroup of
 // kChainThreads threads walks slices k0..k1-1 in order:
 //   g_n   = Gc(c_n)                    (`steps` explicit steps in LDS)
@@ -437,6 +618,44 @@ static hipError_t launch_step(const TI* in, const float* lb, TO* out, float* out
         hipLaunchKernelGGL((k_fine_step<MODE, true, TI, TO>), dim3(blocks), dim3(kBlock), 0, st,
                            in, lb, out, out2, a);
     return hipGetLastError();
+}
+
+template <int MODE, typename T, int S>
+static void launch_tb_s(const T* in, const float* lb, T* out, const StepArgs& a, hipStream_t st) {
+    const int blocks = (step_waves(a) + 3) / 4;
+    if (a.bc.kind == 2)
+        hipLaunchKernelGGL((k_fine_tb<MODE, false, T, S>), dim3(blocks), dim3(kBlock), 0, st, in,
+                           lb, out, a);
+    else
+        hipLaunchKernelGGL((k_fine_tb<MODE, true, T, S>), dim3(blocks), dim3(kBlock), 0, st, in,
+                           lb, out, a);
+}
+
+template <int MODE, typename T>
+static hipError_t launch_tb(const T* in, const float* lb, T* out, const StepArgs& a, int S,
+                            hipStream_t st) {
+    switch (S) {
+        case 1: launch_tb_s<MODE, T, 1>(in, lb, out, a, st); break;
+        case 2: launch_tb_s<MODE, T, 2>(in, lb, out, a, st); break;
+        case 3: launch_tb_s<MODE, T, 3>(in, lb, out, a, st); break;
+        case 4: launch_tb_s<MODE, T, 4>(in, lb, out, a, st); break;
+        case 5: launch_tb_s<MODE, T, 5>(in, lb, out, a, st); break;
+        case 6: launch_tb_s<MODE, T, 6>(in, lb, out, a, st); break;
+        case 7: launch_tb_s<MODE, T, 7>(in, lb, out, a, st); break;
+        case 8: launch_tb_s<MODE, T, 8>(in, lb, out, a, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fine_tb_f32(const float* in, const float* lb, float* out, const StepArgs& a,
+                              int S, hipStream_t st) {
+    return launch_tb<MODE_INCR, float>(in, lb, out, a, S, st);
+}
+
+hipError_t launch_fine_tb_f64(const double* in, double* out, const StepArgs& a, int S,
+                              hipStream_t st) {
+    return launch_tb<MODE_DIRECT, double>(in, nullptr, out, a, S, st);
 }
 
 hipError_t launch_fine_step_f64(const double* in, double* out, const StepArgs& a, hipStream_t st) {

@@ -25,6 +25,8 @@ namespace pr {
 hipError_t launch_fine_step_f64(const double*, double*, const StepArgs&, hipStream_t);
 hipError_t launch_fine_step_f32(const float*, const float*, float*, const StepArgs&, hipStream_t);
 hipError_t launch_fine_prep(const double*, float*, float*, const StepArgs&, hipStream_t);
+hipError_t launch_fine_tb_f32(const float*, const float*, float*, const StepArgs&, int, hipStream_t);
+hipError_t launch_fine_tb_f64(const double*, double*, const StepArgs&, int, hipStream_t);
 hipError_t chain_set_lds(int);
 hipError_t launch_chain(const double*, const void*, double*, double*, double*, float*,
                         const ChainArgs&, hipStream_t);
@@ -162,6 +164,9 @@ struct pr_solver {
     std::vector<hipEvent_t> step_ev;   // PR_FLAG_TIME_STEPS: a pair per step launch
     int step_ev_used = 0;
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
+    int fuse = 4;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
+    int64_t sweep_launches = 0;        // step launches of the last fine_sweep
+    double sweep_bytes = 0;            // their algorithmic bytes
     std::string err;
 
     template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -201,6 +206,22 @@ StepArgs step_args(pr_solver* s, const Grid& g, const Bc& bc, double dt, int fir
     return a;
 }
 
+// Launch geometry of the temporally blocked step kernel for S fused steps:
+// strips of 64 - 2S output columns, row chunks sized so that a launch has
+// enough wavefronts to fill the chip.
+StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, int step, int S) {
+    StepArgs a = step_args(s, g, s->bcf, dt, first, count, step);
+    const int W = kWave - 2 * S;
+    a.nstrips = (g.nin + W - 1) / W;
+    long long target = 6144;
+    long long rows = (long long)g.nin * a.nstrips * count / target;
+    rows = std::max<long long>(8, std::min<long long>(128, rows));
+    if (s->rows_override > 0) rows = s->rows_override;
+    a.rows = (int)std::min<long long>(rows, g.nin);
+    a.nchunks = (g.nin + a.rows - 1) / a.rows;
+    return a;
+}
+
 // F over slices [first, first+count) from base U (interior layout, slice
 // `first` at U + first*stride).  FP32: result increments land in *dres (dA or
 // dB); FP64: the state lands in *wres.  `tmp` selects the single-slice
@@ -216,16 +237,20 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
         HIPCHK(launch_fine_prep(Ubase + (long long)first * g.stride, Lb, A, a, s->stream));
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
-        for (int q = 1; q < s->mF; ++q) {
-            a.step = q;
+        for (int q = 1; q < s->mF;) {
+            const int S = std::min(s->fuse, s->mF - q);
+            StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
             const bool tv = step_ms && s->step_ev_used + 2 <= (int)s->step_ev.size();
             if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
-            HIPCHK(launch_fine_step_f32(A, Lb, B, a, s->stream));
+            HIPCHK(launch_fine_tb_f32(A, Lb, B, b, S, s->stream));
             if (tv) {
                 HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
                 s->step_ev_used += 2;
             }
+            s->sweep_launches += 1;
+            s->sweep_bytes += 12.0 * S * (double)count * g.nin * g.nin;
             std::swap(A, B);
+            q += S;
         }
         if (step_ms && s->events) {
             HIPCHK(hipEventRecord(s->ev[5], s->stream));
@@ -234,19 +259,22 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
     } else {
         double* A = s->at<double>(tmp ? s->L.twA : s->L.wA) + off;
         double* B = s->at<double>(tmp ? s->L.twB : s->L.wB) + off;
-        StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
-        for (int q = 0; q < s->mF; ++q) {
-            a.step = q;
+        for (int q = 0; q < s->mF;) {
+            const int S = std::min(s->fuse, s->mF - q);
+            StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
             const bool tv = step_ms && s->step_ev_used + 2 <= (int)s->step_ev.size();
             if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
-            HIPCHK(launch_fine_step_f64(q == 0 ? Ubase + (long long)first * g.stride : A, q == 0 ? A : B,
-                                        a, s->stream));
+            HIPCHK(launch_fine_tb_f64(q == 0 ? Ubase + (long long)first * g.stride : A,
+                                      q == 0 ? A : B, b, S, s->stream));
             if (tv) {
                 HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
                 s->step_ev_used += 2;
             }
+            s->sweep_launches += 1;
+            s->sweep_bytes += 16.0 * S * (double)count * g.nin * g.nin;
             if (q > 0) std::swap(A, B);
+            q += S;
         }
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[5], s->stream));
         *wres = A - off;
@@ -332,6 +360,8 @@ double host_ring_max(const pr_solver* s, double tau) {
 pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
     const Grid& g = s->fg;
     double* U = s->U(0);
+    s->sweep_launches = 0;
+    s->sweep_bytes = 0;
     HIPCHK(launch_payoff(U, g, s->bcf, s->stream));
     for (int n = 0; n < s->N; ++n) {
         const float* d = nullptr;
@@ -348,7 +378,8 @@ pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
     HIPCHK(hipStreamSynchronize(s->stream));
     if (st) {
         st->fine_point_steps = (int64_t)s->N * s->mF * g.nin * g.nin;
-        st->fine_step_launches = (int64_t)s->N * (s->fp32 ? s->mF - 1 : s->mF);
+        st->fine_step_launches = s->sweep_launches;
+        st->fine_step_bytes = s->sweep_bytes;
     }
     return PR_OK;
 }
@@ -369,9 +400,9 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
     double* Unext = s->U(1);
     double t_fine = 0, t_chain = 0, t_corr = 0, t_steps = 0, step_bytes = 0;
     int64_t launches = 0, psteps = 0;
-    // algorithmic bytes of one explicit step per interior node: FP32 increment
-    // form reads d and Lb and writes d (12 B); FP64 reads and writes u (16 B)
-    const double bpp = s->fp32 ? 12.0 : 16.0;
+    // algorithmic bytes of one explicit step per interior node (counted by
+    // fine_sweep): FP32 increment form reads d and Lb and writes d (12 B);
+    // FP64 reads and writes u (16 B)
 
     // ---- initialisation: U^0_0 = payoff, U^0_{n+1} = G(U^0_n)
     HIPCHK(launch_payoff(Ucur, g, s->bcf, s->stream));
@@ -399,12 +430,13 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
         const float* d = nullptr;
         const double* w = nullptr;
         if (s->events) HIPCHK(hipEventRecord(s->ev[0], s->stream));
+        s->sweep_launches = 0;
+        s->sweep_bytes = 0;
         pr_status r = fine_sweep(s, Ucur, k, N - k, false, &d, &w, &t_steps);
         if (r != PR_OK) return r;
-        const int nsteps = s->fp32 ? s->mF - 1 : s->mF;
-        launches += nsteps;
+        launches += s->sweep_launches;
         psteps += (int64_t)(N - k) * s->mF * g.nin * g.nin;
-        step_bytes += (double)nsteps * (N - k) * g.nin * g.nin * bpp;
+        step_bytes += s->sweep_bytes;
         const void* Fold = s->fp32 ? (const void*)d : (const void*)w;
         if (s->events) HIPCHK(hipEventRecord(s->ev[1], s->stream));
         // ---- chain + correction
@@ -600,6 +632,7 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     s->L = L;
     s->ring_max_T = host_ring_max(s, model->T);
     if (const char* e = std::getenv("PR_STEP_ROWS")) s->rows_override = std::atoi(e);
+    if (const char* e = std::getenv("PR_STEP_FUSE")) s->fuse = std::max(1, std::min(8, std::atoi(e)));
     if (!s->fineg) {
         hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));
         if (e != hipSuccess) {
