@@ -34,6 +34,7 @@ BC_DISCOUNTED_PAYOFF = 1
 BC_EXACT = 2
 G_NUMERICAL = 0
 G_FINE = 1
+G_LOD = 2
 
 
 def build(force: bool = True) -> str:
@@ -115,6 +116,8 @@ def lib():
             "orc_parareal_bs": (C.c_int32, [P, P, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                             C.c_int32, C.c_int32, C.c_double, C.c_int32, D, D]),
             "orc_num_threads": (C.c_int32, []),
+            "orc_lod_step_ring": (None, [P, C.c_double, D, D, D]),
+            "orc_lod": (None, [P, C.c_int, C.c_double, C.c_double, D, D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -213,6 +216,25 @@ def coarse(pf: Problem, pc_: Problem, m: int, dt: float, tau0: float, u: np.ndar
     out = _grid(pf)
     a, b = pf.c(), pc_.c()
     lib().orc_coarse(C.byref(a), C.byref(b), m, dt, tau0, _dp(u), _dp(out))
+    return out
+
+
+def lod_step_ring(p: Problem, dt: float, u: np.ndarray, ring1: np.ndarray) -> np.ndarray:
+    """One locally one-dimensional implicit step; ring1's ring = values at the new time."""
+    u = _grid(p, u)
+    ring1 = _grid(p, ring1)
+    out = _grid(p)
+    pc = p.c()
+    lib().orc_lod_step_ring(C.byref(pc), dt, _dp(u), _dp(ring1), _dp(out))
+    return out
+
+
+def lod(p: Problem, m: int, dt: float, tau0: float, u: np.ndarray) -> np.ndarray:
+    """Same-grid coarse propagator: m LOD implicit steps from tau0."""
+    u = _grid(p, u)
+    out = _grid(p)
+    pc = p.c()
+    lib().orc_lod(C.byref(pc), m, dt, tau0, _dp(u), _dp(out))
     return out
 
 

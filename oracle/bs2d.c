@@ -271,6 +271,121 @@ void orc_coarse(const orc_problem* pf, const orc_problem* pc, int m, double dt, 
 }
 
 /* ---------------------------------------------------------------------------
+ * Same-grid coarse propagator: locally one-dimensional implicit Euler.
+ *
+ * The paper's numerical coarse propagator is implicit Euler on the fine grid
+ * with a larger time step (Sec. 3.2: coarse step 0.1, fine step a third of
+ * it).  Here each implicit step is split by direction (locally one-
+ * dimensional, LOD):
+ *   Lx = alpha D_xx + mu D_x - r/2,   Ly = beta D_yy + nu D_y - r/2,
+ *   Lxy = gamma D_xy (the four-corner mixed difference), L = Lx + Ly + Lxy,
+ *   v   = u + dt Lxy u                            (explicit mixed term)
+ *   (I - dt Lx) w  = v      along each interior column j (x lines)
+ *   (I - dt Ly) u+ = w      along each interior row i    (y lines)
+ * with u+ = g(tau1) on the ring, and on the two ring rows of the x stage the
+ * end values w = (I - dt Ly) g(tau1), so that the step solves exactly
+ *   (I - dt Ly)(I - dt Lx) u+ = u + dt Lxy u   at interior nodes.
+ * Every line system is tridiagonal and solved by the Thomas algorithm.
+ * ------------------------------------------------------------------------- */
+
+/* Solve a_k x_{k-1} + b_k x_k + c_k x_{k+1} = d_k, k = 0..n-1, with x_{-1} =
+ * xlo and x_n = xhi given; d is overwritten by the solution. */
+static void thomas(int n, const double* a, const double* b, const double* c, double* d,
+                   double xlo, double xhi, double* cp)
+{
+    d[0] -= a[0] * xlo;
+    d[n - 1] -= c[n - 1] * xhi;
+    cp[0] = c[0] / b[0];
+    d[0] = d[0] / b[0];
+    for (int k = 1; k < n; ++k) {
+        double den = b[k] - a[k] * cp[k - 1];
+        cp[k] = c[k] / den;
+        d[k] = (d[k] - a[k] * d[k - 1]) / den;
+    }
+    for (int k = n - 2; k >= 0; --k) d[k] -= cp[k] * d[k + 1];
+}
+
+/* One LOD step from u (ring at the old time) to out; ring1 holds the ring
+ * values at the new time (only its ring entries are read). */
+void orc_lod_step_ring(const orc_problem* p, double dt, const double* u, const double* ring1,
+                       double* out)
+{
+    const int M = p->M, n = M - 2;
+    const double a1 = 0.5 * p->sigma1 * p->sigma1, a2 = 0.5 * p->sigma2 * p->sigma2;
+    const double g12 = 0.25 * p->rho * p->sigma1 * p->sigma2, hr = 0.5 * p->r, r = p->r;
+    double* v = (double*)malloc(sizeof(double) * (size_t)M * M);
+    double *la = (double*)malloc(sizeof(double) * n), *lb = (double*)malloc(sizeof(double) * n);
+    double *lc = (double*)malloc(sizeof(double) * n), *ld = (double*)malloc(sizeof(double) * n);
+    double* cp = (double*)malloc(sizeof(double) * n);
+    /* v = u + dt Lxy u */
+    for (int i = 1; i < M - 1; ++i)
+        for (int j = 1; j < M - 1; ++j) {
+            const double* c = u + (size_t)i * M + j;
+            v[(size_t)i * M + j] = c[0] + dt * g12 * i * j * (c[M + 1] + c[-M - 1] - c[M - 1] - c[-M + 1]);
+        }
+    /* (I - dt Ly) g(tau1) on the ring rows i = 0 and i = M-1 */
+    double* wlo = (double*)malloc(sizeof(double) * M);
+    double* whi = (double*)malloc(sizeof(double) * M);
+    for (int j = 1; j < M - 1; ++j) {
+        const double be = a2 * j * j, nu = hr * j;
+        const double* g0 = ring1 + j;
+        const double* g1 = ring1 + (size_t)(M - 1) * M + j;
+        wlo[j] = g0[0] - dt * (be * (g0[1] - 2.0 * g0[0] + g0[-1]) + nu * (g0[1] - g0[-1]) - 0.5 * r * g0[0]);
+        whi[j] = g1[0] - dt * (be * (g1[1] - 2.0 * g1[0] + g1[-1]) + nu * (g1[1] - g1[-1]) - 0.5 * r * g1[0]);
+    }
+    /* x lines: (I - dt Lx) w = v, unknowns i = 1..M-2 */
+    for (int j = 1; j < M - 1; ++j) {
+        for (int k = 0; k < n; ++k) {
+            const int i = k + 1;
+            const double al = a1 * i * i, mu = hr * i;
+            la[k] = -dt * (al - mu);
+            lb[k] = 1.0 + dt * (2.0 * al + 0.5 * r);
+            lc[k] = -dt * (al + mu);
+            ld[k] = v[(size_t)i * M + j];
+        }
+        thomas(n, la, lb, lc, ld, wlo[j], whi[j], cp);
+        for (int k = 0; k < n; ++k) v[(size_t)(k + 1) * M + j] = ld[k];   /* v now holds w */
+    }
+    /* y lines: (I - dt Ly) u+ = w, unknowns j = 1..M-2 */
+    for (int i = 1; i < M - 1; ++i) {
+        for (int k = 0; k < n; ++k) {
+            const int j = k + 1;
+            const double be = a2 * j * j, nu = hr * j;
+            la[k] = -dt * (be - nu);
+            lb[k] = 1.0 + dt * (2.0 * be + 0.5 * r);
+            lc[k] = -dt * (be + nu);
+            ld[k] = v[(size_t)i * M + j];
+        }
+        thomas(n, la, lb, lc, ld, ring1[(size_t)i * M], ring1[(size_t)i * M + M - 1], cp);
+        for (int k = 0; k < n; ++k) out[(size_t)i * M + k + 1] = ld[k];
+    }
+    for (int k = 0; k < M; ++k) {
+        out[k] = ring1[k];
+        out[(size_t)(M - 1) * M + k] = ring1[(size_t)(M - 1) * M + k];
+        out[(size_t)k * M] = ring1[(size_t)k * M];
+        out[(size_t)k * M + M - 1] = ring1[(size_t)k * M + M - 1];
+    }
+    free(v); free(la); free(lb); free(lc); free(ld); free(cp); free(wlo); free(whi);
+}
+
+/* LOD coarse propagator over one slice: m steps of dt from tau0, ring g. */
+void orc_lod(const orc_problem* p, int m, double dt, double tau0, const double* in, double* out)
+{
+    const size_t n = (size_t)p->M * p->M;
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* b = (double*)malloc(sizeof(double) * n);
+    double* ring = (double*)malloc(sizeof(double) * n);
+    memcpy(a, in, sizeof(double) * n);
+    for (int q = 0; q < m; ++q) {
+        orc_set_boundary(p, tau0 + (double)(q + 1) * dt, ring);
+        orc_lod_step_ring(p, dt, a, ring, b);
+        double* t = a; a = b; b = t;
+    }
+    memcpy(out, a, sizeof(double) * n);
+    free(a); free(b); free(ring);
+}
+
+/* ---------------------------------------------------------------------------
  * Parareal, Eq. (parareal), Sec. 3.1, for a generic state of `len` doubles and
  * propagators given as callbacks prop(ctx, n, in, out) over slice n.
  *
@@ -346,7 +461,7 @@ int32_t orc_parareal(int64_t len, int32_t N, const double* u0, orc_prop_fn F, vo
 /* ---------------------------------------------------------------------------
  * The Black-Scholes instance of the driver above.
  * ------------------------------------------------------------------------- */
-enum { ORC_G_NUMERICAL = 0, ORC_G_FINE = 1 };
+enum { ORC_G_NUMERICAL = 0, ORC_G_FINE = 1, ORC_G_LOD = 2 };
 
 typedef struct {
     orc_problem fine, coarse;
@@ -367,6 +482,8 @@ static void bs_G(void* ctx, int32_t n, const double* in, double* out)
     double dT = c->T / c->N;
     if (c->coarse_kind == ORC_G_FINE)
         orc_fine(&c->fine, c->mF, dT / c->mF, n * dT, in, out);
+    else if (c->coarse_kind == ORC_G_LOD)
+        orc_lod(&c->fine, c->mG, dT / c->mG, n * dT, in, out);
     else
         orc_coarse(&c->fine, &c->coarse, c->mG, dT / c->mG, n * dT, in, out);
 }
