@@ -70,13 +70,23 @@ enum { PR_BC_FORWARD_INTRINSIC = 0, /* basket: max(w1 S1 + w2 S2 - K e^{-r tau},
 
 /* Coarse propagator. */
 enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilinear */
-       PR_G_FINE = 2       /* G := F (test mode: Parareal stops after one iteration) */ };
+       PR_G_FINE = 2,      /* G := F (test mode: Parareal stops after one iteration) */
+       PR_G_LOD = 3        /* implicit Euler on the fine grid with coarse_steps steps per
+                              slice (default 2), split by direction: the explicit mixed
+                              term, then tridiagonal x lines and y lines (Sec. 3.2's
+                              coarse propagator is implicit Euler with a larger step) */ };
 
 /* Option flags.  PR_FLAG_TIME_STEPS: bracket every explicit fine-step launch
  * with HIP events on the solver's stream and report their summed durations in
  * pr_stats.t_step_kernels_ms (otherwise the field brackets the whole run of
  * step launches, gaps included). */
 #define PR_FLAG_TIME_STEPS 1u
+/* PR_FLAG_GRAPH: capture the initial sweep and each Parareal iteration k (its
+ * fine sweep, coarse chain, correction and norm) into a HIP graph once, on a
+ * private capture stream, and replay it on the solver's stream; graphs are
+ * cached per k and reused by later solves of the same solver.  Phase timings
+ * then cover whole iterations (t_fine_ms) and PR_FLAG_TIME_STEPS is ignored. */
+#define PR_FLAG_GRAPH 2u
 
 /* Arithmetic of the fine and numerical coarse propagators. */
 enum { PR_FP64 = 0, /* everything in FP64 */
@@ -110,8 +120,8 @@ typedef struct {
     int32_t precision;      /* PR_FP64 or PR_FP32 */
     int32_t fine_steps;     /* explicit steps per slice; 0 => planned from cfl */
     int32_t coarse_kind;    /* PR_G_* */
-    int32_t coarse_n;       /* coarse nodes per side; (n-1) % (coarse_n-1) == 0 */
-    int32_t coarse_steps;   /* coarse steps per slice; 0 => planned from cfl */
+    int32_t coarse_n;       /* PR_G_NUMERICAL: coarse nodes per side; (n-1) % (coarse_n-1) == 0 */
+    int32_t coarse_steps;   /* coarse steps per slice; 0 => planned from cfl (PR_G_LOD: 2) */
     double cfl;             /* planned dt = dT / ceil(dT / (cfl * dt_stable)); (0, 1] */
     uint32_t flags;         /* PR_FLAG_* bits */
     int32_t pad_;

@@ -17,10 +17,11 @@ PR_MAX_SLICES = 1024
 PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_ENOTCONV, PR_ENONFINITE, PR_EMODEL = range(8)
 PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE = 0, 1
 PR_BC_FORWARD_INTRINSIC, PR_BC_DISCOUNTED_PAYOFF, PR_BC_EXACT = 0, 1, 2
-PR_G_NUMERICAL, PR_G_FINE = 0, 2
+PR_G_NUMERICAL, PR_G_FINE, PR_G_LOD = 0, 2, 3
 PR_FP64, PR_FP32 = 0, 1
 PR_OP_FINE, PR_OP_COARSE = 0, 1
 PR_FLAG_TIME_STEPS = 1
+PR_FLAG_GRAPH = 2
 
 
 class pr_grid(C.Structure):

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/parareal.h"
@@ -40,6 +41,9 @@ hipError_t launch_prolong(const double*, double*, const Grid&, int, int, int, in
 hipError_t launch_pack(const double*, double*, const Grid&, hipStream_t);
 hipError_t launch_unpack(const double*, double*, const Grid&, const Bc&, double, hipStream_t);
 hipError_t launch_finalize(const double*, const float*, double*, const Grid&, hipStream_t);
+hipError_t launch_lod_slice(const double*, double*, double*, double*, double*, const Grid&,
+                            const Coef&, const Bc&, double, double, int, hipStream_t);
+hipError_t lod_set_lds(int);
 }  // namespace pr
 
 using namespace pr;
@@ -81,7 +85,8 @@ double gershgorin_dt(int n, const pr_model& m) {
 }
 
 struct Layout {
-    uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red, total;
+    uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
+        lw0, lw1, lwb, total;
 };
 
 bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
@@ -91,7 +96,8 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
     if (!(g->s_max > 0.0)) return fail("grid.s_max must be > 0");
     if (o->n_slices < 1 || o->n_slices > PR_MAX_SLICES) return fail("n_slices out of range");
     if (o->precision != PR_FP64 && o->precision != PR_FP32) return fail("unknown precision");
-    if (o->coarse_kind != PR_G_NUMERICAL && o->coarse_kind != PR_G_FINE)
+    if (o->coarse_kind != PR_G_NUMERICAL && o->coarse_kind != PR_G_FINE &&
+        o->coarse_kind != PR_G_LOD)
         return fail("unknown coarse_kind");
     if (o->coarse_kind == PR_G_NUMERICAL) {
         if (o->coarse_n < 3) return fail("coarse_n must be >= 3");
@@ -101,6 +107,8 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
         if (o->precision == PR_FP64 && o->coarse_n > 89)
             return fail("coarse_n above 89 is not supported in FP64");
     }
+    if (o->coarse_kind == PR_G_LOD && g->n - 2 > 2048)
+        return fail("PR_G_LOD supports up to 2050 nodes per side");
     if (o->fine_steps < 0 || o->coarse_steps < 0) return fail("negative step count");
     if ((o->fine_steps == 0 || o->coarse_steps == 0) && !(o->cfl > 0.0 && o->cfl <= 1.0))
         return fail("cfl must be in (0, 1] when a step count is planned");
@@ -114,7 +122,9 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     const uint64_t N = o->n_slices;
     const uint64_t sd = (uint64_t)fg.stride * 8, sf = (uint64_t)fg.stride * 4;
     const bool fp32 = o->precision == PR_FP32;
-    const bool fineg = o->coarse_kind == PR_G_FINE;
+    const bool gfine = o->coarse_kind == PR_G_FINE;
+    const bool lod = o->coarse_kind == PR_G_LOD;
+    const bool fineg = gfine || lod;   // G runs on the fine grid (chain over fine slices)
     const uint64_t nc = fineg ? 0 : (uint64_t)o->coarse_n;
     Layout L{};
     uint64_t p = 0;
@@ -131,12 +141,15 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.cst = take(nc * nc * 8);
     L.lbc = take(nc * nc * 4);
     L.Gf = take(fineg ? N * sd : 0);
-    L.tA = take(fineg && fp32 ? sf : 0);
-    L.tB = take(fineg && fp32 ? sf : 0);
-    L.tLb = take(fineg && fp32 ? sf : 0);
-    L.twA = take(fineg && !fp32 ? sd : 0);
-    L.twB = take(fineg && !fp32 ? sd : 0);
+    L.tA = take(gfine && fp32 ? sf : 0);
+    L.tB = take(gfine && fp32 ? sf : 0);
+    L.tLb = take(gfine && fp32 ? sf : 0);
+    L.twA = take(gfine && !fp32 ? sd : 0);
+    L.twB = take(gfine && !fp32 ? sd : 0);
     L.tg = take(fineg ? sd : 0);
+    L.lw0 = take(lod ? sd : 0);
+    L.lw1 = take(lod ? sd : 0);
+    L.lwb = take(lod ? sd : 0);
     L.red = take(64);
     L.total = p;
     return L;
@@ -155,7 +168,7 @@ struct pr_solver {
     Bc bcf{}, bcc{};
     int N = 0, nc = 0, q = 1, mF = 0, mG = 0, maxit = 0;
     double dT = 0, dtF = 0, dtG = 0, ring_max_T = 0;
-    bool fp32 = false, fineg = false;
+    bool fp32 = false, fineg = false, lod = false;
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
     Layout L{};
@@ -165,8 +178,14 @@ struct pr_solver {
     int step_ev_used = 0;
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
     int fuse = 4;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
+    std::map<int, int64_t> graph_launches;   // step launches captured in graph k
+    std::map<int, double> graph_bytes;
     int64_t sweep_launches = 0;        // step launches of the last fine_sweep
     double sweep_bytes = 0;            // their algorithmic bytes
+    bool graph = false;                // PR_FLAG_GRAPH
+    hipStream_t cap_stream = nullptr;  // capture vehicle (never executes work)
+    std::map<int, hipGraphExec_t> graphs;   // key -1: initial sweep, k: iteration k
+    std::map<int, hipGraph_t> graph_defs;
     std::string err;
 
     template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -386,11 +405,126 @@ pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
 
 // The G = F chain for slice n: g = F(U^{k+1}_n) into tg (one slice).
 pr_status fine_g(pr_solver* s, const double* Uslice_base_all, int n, double* gout) {
+    if (s->lod) {
+        HIPCHK(launch_lod_slice(Uslice_base_all + (long long)n * s->fg.stride, gout,
+                                s->at<double>(s->L.lw0), s->at<double>(s->L.lw1),
+                                s->at<double>(s->L.lwb), s->fg, s->coef, s->bcf, s->dtG,
+                                n * s->dT, s->mG, s->stream));
+        return PR_OK;
+    }
     const float* d = nullptr;
     const double* w = nullptr;
     pr_status r = fine_sweep(s, Uslice_base_all, n, 1, true, &d, &w, nullptr);
     if (r != PR_OK) return r;
     return fine_result_to_state(s, Uslice_base_all + (long long)n * s->fg.stride, d, w, gout);
+}
+
+// Initial coarse sweep: U_0 = payoff, U_{n+1} = G(U_n) (stream-ordered, no host sync).
+pr_status init_phase(pr_solver* s, double* Ucur, double* Unext) {
+    const Grid& g = s->fg;
+    const int N = s->N;
+    HIPCHK(launch_payoff(Ucur, g, s->bcf, s->stream));
+    HIPCHK(hipMemcpyAsync(Unext, Ucur, (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->fineg) {
+        double* Gf = s->at<double>(s->L.Gf);
+        for (int n = 0; n < N; ++n) {
+            pr_status r = fine_g(s, Ucur, n, Ucur + (long long)(n + 1) * g.stride);
+            if (r != PR_OK) return r;
+            HIPCHK(hipMemcpyAsync(Gf + (long long)n * g.stride, Ucur + (long long)(n + 1) * g.stride,
+                                  (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+        }
+    } else {
+        ChainArgs ca = chain_args(s, 0, N, 1);
+        HIPCHK(launch_chain(Ucur, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+                            s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
+        HIPCHK(launch_prolong(s->at<double>(s->L.Gold), Ucur, g, s->nc, s->q, 0, N, s->stream));
+    }
+    return PR_OK;
+}
+
+// Iteration k: F sweep over slices k..N-1, coarse chain, correction + norm
+// into Unext (stream-ordered, no host sync).  step_ms != nullptr enables the
+// per-phase and per-launch timing events.
+pr_status iteration_phase(pr_solver* s, int k, double* Ucur, double* Unext, double* step_ms) {
+    const Grid& g = s->fg;
+    const int N = s->N;
+    const float* d = nullptr;
+    const double* w = nullptr;
+    const bool ev = step_ms != nullptr && s->events;
+    pr_status r = fine_sweep(s, Ucur, k, N - k, false, &d, &w, step_ms);
+    if (r != PR_OK) return r;
+    const void* Fold = s->fp32 ? (const void*)d : (const void*)w;
+    if (ev) HIPCHK(hipEventRecord(s->ev[1], s->stream));
+    unsigned long long* red = s->red();
+    HIPCHK(launch_zero_red(red, s->stream));
+    if (k > 0)
+        HIPCHK(hipMemcpyAsync(Unext + (long long)k * g.stride, Ucur + (long long)k * g.stride,
+                              (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->fineg) {
+        double* tg = s->at<double>(s->L.tg);
+        double* Gf = s->at<double>(s->L.Gf);
+        for (int n = k; n < N; ++n) {
+            r = fine_g(s, Unext, n, tg);
+            if (r != PR_OK) return r;
+            HIPCHK(launch_correct(Ucur, Fold, nullptr, tg, Gf, Unext, red, g, n, n + 1, N, 0, 1,
+                                  s->fp32, 1, s->stream));
+        }
+        if (ev) HIPCHK(hipEventRecord(s->ev[2], s->stream));
+    } else {
+        ChainArgs ca = chain_args(s, k, N, 0);
+        HIPCHK(launch_chain(Ucur, Fold, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+                            s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
+        if (ev) HIPCHK(hipEventRecord(s->ev[2], s->stream));
+        HIPCHK(launch_correct(Ucur, Fold, s->at<double>(s->L.dcor), nullptr, nullptr, Unext, red,
+                              g, k, N, N, s->nc, s->q, s->fp32, 0, s->stream));
+    }
+    if (ev) HIPCHK(hipEventRecord(s->ev[3], s->stream));
+    return PR_OK;
+}
+
+// Run a phase eagerly, or (PR_FLAG_GRAPH) capture it once on the private
+// capture stream and replay the cached graph on the solver's stream.
+template <class Fn>
+pr_status run_phase(pr_solver* s, int key, Fn&& fn) {
+    if (!s->graph) return fn();
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+        hipStream_t user = s->stream;
+        s->stream = s->cap_stream;
+        s->sweep_launches = 0;
+        s->sweep_bytes = 0;
+        hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            s->stream = user;
+            s->err = std::string("hipStreamBeginCapture: ") + hipGetErrorString(e);
+            return PR_EDEVICE;
+        }
+        pr_status r = fn();
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(s->cap_stream, &gr);
+        s->stream = user;
+        if (r != PR_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return r;
+        }
+        if (e != hipSuccess) {
+            s->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+            return PR_EDEVICE;
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            s->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+            return PR_EDEVICE;
+        }
+        s->graph_defs[key] = gr;
+        s->graph_launches[key] = s->sweep_launches;
+        s->graph_bytes[key] = s->sweep_bytes;
+        it = s->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, s->stream));
+    return PR_OK;
 }
 
 pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
@@ -405,69 +539,33 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
     // FP64 reads and writes u (16 B)
 
     // ---- initialisation: U^0_0 = payoff, U^0_{n+1} = G(U^0_n)
-    HIPCHK(launch_payoff(Ucur, g, s->bcf, s->stream));
-    HIPCHK(hipMemcpyAsync(Unext, Ucur, (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
-    if (s->fineg) {
-        double* Gf = s->at<double>(s->L.Gf);
-        for (int n = 0; n < N; ++n) {
-            pr_status r = fine_g(s, Ucur, n, Ucur + (long long)(n + 1) * g.stride);
-            if (r != PR_OK) return r;
-            HIPCHK(hipMemcpyAsync(Gf + (long long)n * g.stride, Ucur + (long long)(n + 1) * g.stride,
-                                  (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
-        }
-    } else {
-        ChainArgs ca = chain_args(s, 0, N, 1);
-        HIPCHK(launch_chain(Ucur, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor), s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca,
-                            s->stream));
-        HIPCHK(launch_prolong(s->at<double>(s->L.Gold), Ucur, g, s->nc, s->q, 0, N, s->stream));
+    {
+        pr_status r = run_phase(s, -1, [&]() { return init_phase(s, Ucur, Unext); });
+        if (r != PR_OK) return r;
     }
-
     int K = 0;
     pr_status status = PR_OK;
     double inc = 0, scale = 0;
     for (int k = 0; k < s->maxit && k < N; ++k) {
-        // ---- F sweep over active slices k..N-1
-        const float* d = nullptr;
-        const double* w = nullptr;
-        if (s->events) HIPCHK(hipEventRecord(s->ev[0], s->stream));
+        // ---- F sweep over active slices k..N-1, chain, correction + norm
         s->sweep_launches = 0;
         s->sweep_bytes = 0;
-        pr_status r = fine_sweep(s, Ucur, k, N - k, false, &d, &w, &t_steps);
+        if (s->events) HIPCHK(hipEventRecord(s->ev[0], s->stream));
+        pr_status r = run_phase(s, k, [&]() {
+            return iteration_phase(s, k, Ucur, Unext, s->graph ? nullptr : &t_steps);
+        });
         if (r != PR_OK) return r;
-        launches += s->sweep_launches;
+        if (s->graph && s->events) HIPCHK(hipEventRecord(s->ev[3], s->stream));
+        launches += s->graph ? s->graph_launches[k] : s->sweep_launches;
+        step_bytes += s->graph ? s->graph_bytes[k] : s->sweep_bytes;
         psteps += (int64_t)(N - k) * s->mF * g.nin * g.nin;
-        step_bytes += s->sweep_bytes;
-        const void* Fold = s->fp32 ? (const void*)d : (const void*)w;
-        if (s->events) HIPCHK(hipEventRecord(s->ev[1], s->stream));
-        // ---- chain + correction
         unsigned long long* red = s->red();
-        HIPCHK(launch_zero_red(red, s->stream));
-        if (k > 0)
-            HIPCHK(hipMemcpyAsync(Unext + (long long)k * g.stride, Ucur + (long long)k * g.stride,
-                                  (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
-        if (s->fineg) {
-            double* tg = s->at<double>(s->L.tg);
-            double* Gf = s->at<double>(s->L.Gf);
-            for (int n = k; n < N; ++n) {
-                r = fine_g(s, Unext, n, tg);
-                if (r != PR_OK) return r;
-                HIPCHK(launch_correct(Ucur, Fold, nullptr, tg, Gf, Unext, red, g, n, n + 1, N, 0,
-                                      1, s->fp32, 1, s->stream));
-            }
-            if (s->events) HIPCHK(hipEventRecord(s->ev[2], s->stream));
-        } else {
-            ChainArgs ca = chain_args(s, k, N, 0);
-            HIPCHK(launch_chain(Ucur, Fold, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
-                                s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
-            if (s->events) HIPCHK(hipEventRecord(s->ev[2], s->stream));
-            HIPCHK(launch_correct(Ucur, Fold, s->at<double>(s->L.dcor), nullptr, nullptr, Unext,
-                                  red, g, k, N, N, s->nc, s->q, s->fp32, 0, s->stream));
-        }
-        if (s->events) HIPCHK(hipEventRecord(s->ev[3], s->stream));
         unsigned long long hred[3];
         HIPCHK(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
-        if (s->events) {
+        if (s->events && s->graph) {
+            t_fine += elapsed(s, 0, 3);
+        } else if (s->events) {
             t_fine += elapsed(s, 0, 1);
             t_chain += elapsed(s, 1, 2);
             t_corr += elapsed(s, 2, 3);
@@ -550,6 +648,7 @@ pr_status parareal_plan(const pr_grid* grid, const pr_model* model, const pr_opt
     if (mf == 0) mf = (int)std::ceil(dT / (opt->cfl * dsf));
     int mg = 0;
     double dsc = 0;
+    if (opt->coarse_kind == PR_G_LOD) mg = opt->coarse_steps > 0 ? opt->coarse_steps : 2;
     if (opt->coarse_kind == PR_G_NUMERICAL) {
         dsc = gershgorin_dt(opt->coarse_n, *model);
         mg = opt->coarse_steps;
@@ -603,7 +702,8 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     s->N = opt->n_slices;
     s->maxit = opt->max_iters > 0 ? std::min(opt->max_iters, s->N) : s->N;
     s->fp32 = opt->precision == PR_FP32;
-    s->fineg = opt->coarse_kind == PR_G_FINE;
+    s->lod = opt->coarse_kind == PR_G_LOD;
+    s->fineg = opt->coarse_kind == PR_G_FINE || s->lod;
     s->nc = s->fineg ? 0 : opt->coarse_n;
     s->q = s->fineg ? 1 : (grid->n - 1) / (opt->coarse_n - 1);
     s->mF = mf;
@@ -640,10 +740,21 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
             return PR_EDEVICE;
         }
     }
+    if (s->lod && lod_set_lds(s->fg.nin) != hipSuccess) {
+        delete s;
+        return PR_EDEVICE;
+    }
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     s->events = ok;
-    if (opt->flags & PR_FLAG_TIME_STEPS) {
+    s->graph = (opt->flags & PR_FLAG_GRAPH) != 0;
+    if (s->graph && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        for (auto& e : s->ev)
+            if (e) (void)hipEventDestroy(e);
+        delete s;
+        return PR_EDEVICE;
+    }
+    if ((opt->flags & PR_FLAG_TIME_STEPS) && !s->graph) {
         s->step_ev.resize(2 * (size_t)mf, nullptr);
         for (auto& e : s->step_ev)
             if (hipEventCreate(&e) != hipSuccess) {
@@ -713,7 +824,7 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
     double* Us = U + (long long)slice * g.stride;
     double* Us1 = U + (long long)(slice + 1) * g.stride;
     HIPCHK(launch_pack(in, Us, g, s->stream));
-    if (op == PR_OP_FINE || s->fineg) {
+    if (op == PR_OP_FINE) {
         const float* d = nullptr;
         const double* w = nullptr;
         pr_status r = fine_sweep(s, U, slice, 1, false, &d, &w, nullptr);
@@ -721,10 +832,13 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
         r = fine_result_to_state(s, Us, d ? d + (long long)slice * g.stride : nullptr,
                                  w ? w + (long long)slice * g.stride : nullptr, Us1);
         if (r != PR_OK) return r;
+    } else if (s->fineg) {
+        pr_status r = fine_g(s, U, slice, Us1);
+        if (r != PR_OK) return r;
     } else {
         ChainArgs ca = chain_args(s, slice, slice + 1, 1);
-        HIPCHK(launch_chain(U, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor), s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca,
-                            s->stream));
+        HIPCHK(launch_chain(U, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+                            s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
         HIPCHK(launch_prolong(s->at<double>(s->L.Gold), U, g, s->nc, s->q, slice, slice + 1,
                               s->stream));
     }
@@ -739,6 +853,9 @@ pr_status parareal_destroy(pr_solver* s) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : s->step_ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->graph_defs) (void)hipGraphDestroy(kv.second);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;
     return PR_OK;
 }
