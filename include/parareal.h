@@ -189,6 +189,63 @@ enum { PR_OP_FINE = 0, PR_OP_COARSE = 1 };
 pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* in, double* out);
 
 pr_status parareal_destroy(pr_solver* s);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent Parareal solves (no counterpart
+ * in the paper; the solves are those of parareal_solve).
+ *
+ * A server owns nothing but its streams and a small pinned host pool: the
+ * caller hands it one device arena, and every admitted request gets its
+ * workspace carved out of that arena (first fit, 256-byte aligned) for as
+ * long as it is resident.  Requests are admitted in submission order while
+ * their workspace fits and fewer than max_resident are resident; each
+ * resident request runs on one of n_streams HIP streams, so the kernels of
+ * different requests overlap on the device.  pr_server_progress never blocks:
+ * it looks at which in-flight iterations have finished, decides stop or
+ * continue for each from its 24-byte norm read-back, enqueues the next
+ * iteration or the final write of the result, retires finished requests
+ * (their workspace returns to the arena) and admits waiting ones.  Results
+ * are bitwise those of parareal_solve on the same request.
+ * ------------------------------------------------------------------------- */
+typedef struct pr_server pr_server; /* opaque */
+
+typedef struct {
+    int32_t max_resident; /* cap on resident requests (>= 1) */
+    int32_t n_streams;    /* HIP streams shared by resident requests (1..32) */
+    uint32_t flags;       /* reserved, 0 */
+    int32_t pad_;
+} pr_server_options;
+
+typedef struct {
+    int32_t status;        /* pr_status of the solve */
+    int32_t iters;         /* Parareal iterations K */
+    double last_increment; /* max increment of the last iteration */
+    double latency_ms;     /* submit -> result written (host clock) */
+    double queue_ms;       /* submit -> admission */
+    uint64_t workspace_bytes;
+} pr_request_info;
+
+/* Workspace a request needs inside the arena (0 when the arguments are invalid). */
+uint64_t pr_server_footprint(const pr_grid* grid, const pr_options* opt);
+/* arena: device pointer, 256-byte aligned, owned by the caller. */
+pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_options* opt,
+                           pr_server** out);
+/* Queue one solve; v_out: device pointer to n*n doubles, written when the request
+ * completes.  Arguments are validated here (PR_EINVAL / PR_EUNSTABLE); a request
+ * larger than the whole arena is rejected with PR_ENOMEM.  *id_out identifies it. */
+pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* model,
+                           const pr_payoff* payoff, const pr_options* opt, double* v_out,
+                           int64_t* id_out);
+/* One non-blocking scheduling pass.  Counts are written when the pointers are non-NULL. */
+pr_status pr_server_progress(pr_server* sv, int32_t* n_resident, int32_t* n_queued,
+                             int32_t* n_done);
+/* *done = 1 once the request's result is written; info (may be NULL) is filled then. */
+pr_status pr_server_poll(pr_server* sv, int64_t id, int32_t* done, pr_request_info* info);
+/* Peak resident requests and peak arena bytes in use since creation. */
+pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t* peak_bytes);
+/* Blocks until all submitted work has drained, then releases the streams. */
+pr_status pr_server_destroy(pr_server* sv);
+
 const char* parareal_strerror(pr_status st);
 const char* parareal_last_error(const pr_solver* s);
 int32_t parareal_abi_version(void);

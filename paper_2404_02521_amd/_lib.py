@@ -56,6 +56,17 @@ class pr_stats(C.Structure):
                 ("workspace_bytes", C.c_uint64)]
 
 
+class pr_server_options(C.Structure):
+    _fields_ = [("max_resident", C.c_int32), ("n_streams", C.c_int32), ("flags", C.c_uint32),
+                ("pad_", C.c_int32)]
+
+
+class pr_request_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("last_increment", C.c_double),
+                ("latency_ms", C.c_double), ("queue_ms", C.c_double),
+                ("workspace_bytes", C.c_uint64)]
+
+
 # (name, restype, argtypes) of every exported entry point of include/parareal.h
 SIGNATURES = [
     ("parareal_plan", C.c_int, [C.POINTER(pr_grid), C.POINTER(pr_model), C.POINTER(pr_options),
@@ -72,6 +83,18 @@ SIGNATURES = [
     ("parareal_strerror", C.c_char_p, [C.c_int]),
     ("parareal_last_error", C.c_char_p, [C.c_void_p]),
     ("parareal_abi_version", C.c_int32, []),
+    ("pr_server_footprint", C.c_uint64, [C.POINTER(pr_grid), C.POINTER(pr_options)]),
+    ("pr_server_create", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(pr_server_options),
+                                   C.POINTER(C.c_void_p)]),
+    ("pr_server_submit", C.c_int, [C.c_void_p, C.POINTER(pr_grid), C.POINTER(pr_model),
+                                   C.POINTER(pr_payoff), C.POINTER(pr_options), C.c_void_p,
+                                   C.POINTER(C.c_int64)]),
+    ("pr_server_progress", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32)]),
+    ("pr_server_poll", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
+                                 C.POINTER(pr_request_info)]),
+    ("pr_server_peaks", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
+    ("pr_server_destroy", C.c_int, [C.c_void_p]),
 ]
 
 _lib = None

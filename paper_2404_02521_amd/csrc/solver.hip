@@ -861,3 +861,311 @@ pr_status parareal_destroy(pr_solver* s) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching over a caller-provided device arena.
+// ===========================================================================
+#include <deque>
+
+namespace {
+
+struct Req {
+    int64_t id = 0;
+    pr_grid g{};
+    pr_model m{};
+    pr_payoff p{};
+    pr_options o{};
+    double* v_out = nullptr;
+    uint64_t bytes = 0, off = 0;
+    pr_solver* s = nullptr;
+    int state = 0;   // 0 queued, 1 iteration in flight, 2 result write in flight, 3 done
+    int k = 0;       // iterations completed
+    int slot = -1;   // pinned read-back slot
+    hipEvent_t ev = nullptr;
+    pr_status status = PR_OK;
+    double inc = 0;
+    std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+};
+
+}  // namespace
+
+struct pr_server {
+    char* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    std::map<uint64_t, uint64_t> free_;   // offset -> size of free blocks
+    std::vector<hipStream_t> streams;
+    unsigned long long* pinned = nullptr;  // 4 words per slot
+    std::vector<int> free_slots;
+    std::deque<int64_t> queue;
+    std::map<int64_t, Req> reqs;
+    std::vector<int64_t> resident;
+    int64_t next_id = 1;
+    int max_resident = 1, rr = 0, peak_resident = 0, n_done = 0;
+    uint64_t used = 0, peak_bytes = 0;
+};
+
+namespace {
+
+bool arena_alloc(pr_server* sv, uint64_t bytes, uint64_t* off) {
+    bytes = al(bytes);
+    for (auto it = sv->free_.begin(); it != sv->free_.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const uint64_t rest = it->second - bytes, at = it->first + bytes;
+            sv->free_.erase(it);
+            if (rest) sv->free_[at] = rest;
+            sv->used += bytes;
+            sv->peak_bytes = std::max(sv->peak_bytes, sv->used);
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(pr_server* sv, uint64_t off, uint64_t bytes) {
+    bytes = al(bytes);
+    sv->used -= bytes;
+    auto it = sv->free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != sv->free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        sv->free_.erase(nx);
+    }
+    if (it != sv->free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            sv->free_.erase(it);
+        }
+    }
+}
+
+// Enqueue iteration k of request r and the read-back of its norms.
+pr_status req_enqueue_iteration(pr_server* sv, Req& r) {
+    pr_solver* s = r.s;
+    double* Ucur = s->U(r.k & 1);
+    double* Unext = s->U((r.k + 1) & 1);
+    pr_status st = iteration_phase(s, r.k, Ucur, Unext, nullptr);
+    if (st != PR_OK) return st;
+    HIPCHK(hipMemcpyAsync(sv->pinned + 4 * r.slot, s->red(), 3 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipEventRecord(r.ev, s->stream));
+    return PR_OK;
+}
+
+pr_status req_admit(pr_server* sv, Req& r) {
+    const int si = sv->rr++ % (int)sv->streams.size();
+    pr_options o = r.o;
+    o.flags &= ~(PR_FLAG_GRAPH | PR_FLAG_TIME_STEPS);
+    pr_status st = parareal_create(&r.g, &r.m, &r.p, &o, sv->arena + r.off, r.bytes,
+                                   sv->streams[si], &r.s);
+    if (st != PR_OK) return st;
+    pr_solver* s = r.s;
+    if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) return PR_EDEVICE;
+    r.slot = sv->free_slots.back();
+    sv->free_slots.pop_back();
+    st = init_phase(s, s->U(0), s->U(1));
+    if (st != PR_OK) return st;
+    r.k = 0;
+    r.state = 1;
+    return req_enqueue_iteration(sv, r);
+}
+
+void req_retire(pr_server* sv, Req& r) {
+    if (r.ev) (void)hipEventDestroy(r.ev);
+    r.ev = nullptr;
+    if (r.s) parareal_destroy(r.s);
+    r.s = nullptr;
+    if (r.slot >= 0) sv->free_slots.push_back(r.slot);
+    r.slot = -1;
+    arena_free(sv, r.off, r.bytes);
+    r.state = 3;
+    r.t_done = std::chrono::steady_clock::now();
+    sv->n_done++;
+}
+
+// The iteration of r has finished: stop or continue.
+pr_status req_advance(pr_server* sv, Req& r) {
+    pr_solver* s = r.s;
+    const unsigned long long* h = sv->pinned + 4 * r.slot;
+    double inc, scint;
+    std::memcpy(&inc, &h[0], 8);
+    std::memcpy(&scint, &h[1], 8);
+    r.k += 1;
+    r.inc = inc;
+    const double scale = std::max(scint, s->ring_max_T);
+    const double thr = s->opt.tol_relative ? s->opt.tol * scale : s->opt.tol;
+    bool stop = false;
+    if (h[2]) { r.status = PR_ENONFINITE; stop = true; }
+    else if (inc < thr || r.k == s->N) stop = true;
+    else if (r.k == s->maxit) { r.status = PR_ENOTCONV; stop = true; }
+    if (!stop) return req_enqueue_iteration(sv, r);
+    HIPCHK(launch_unpack(s->U(r.k & 1) + (long long)s->N * s->fg.stride, r.v_out, s->fg, s->bcf,
+                         s->N * s->dT, s->stream));
+    HIPCHK(hipEventRecord(r.ev, s->stream));
+    r.state = 2;
+    return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t pr_server_footprint(const pr_grid* grid, const pr_options* opt) {
+    const uint64_t b = parareal_workspace_bytes(grid, opt);
+    return b ? al(b) : 0;
+}
+
+pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_options* opt,
+                           pr_server** out) {
+    if (!out || !arena || !opt) return PR_EINVAL;
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(arena) % kAlign) return PR_EINVAL;
+    if (opt->max_resident < 1 || opt->n_streams < 1 || opt->n_streams > 32) return PR_EINVAL;
+    pr_server* sv = new (std::nothrow) pr_server();
+    if (!sv) return PR_ENOMEM;
+    sv->arena = reinterpret_cast<char*>(arena);
+    sv->arena_bytes = arena_bytes / kAlign * kAlign;
+    sv->free_[0] = sv->arena_bytes;
+    sv->max_resident = opt->max_resident;
+    for (int i = 0; i < opt->n_streams; ++i) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            pr_server_destroy(sv);
+            return PR_EDEVICE;
+        }
+        sv->streams.push_back(st);
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&sv->pinned),
+                      sizeof(unsigned long long) * 4 * (size_t)sv->max_resident) != hipSuccess) {
+        sv->pinned = nullptr;
+        pr_server_destroy(sv);
+        return PR_EDEVICE;
+    }
+    for (int i = sv->max_resident - 1; i >= 0; --i) sv->free_slots.push_back(i);
+    *out = sv;
+    return PR_OK;
+}
+
+pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* model,
+                           const pr_payoff* payoff, const pr_options* opt, double* v_out,
+                           int64_t* id_out) {
+    if (!sv || !grid || !model || !payoff || !opt || !v_out || !id_out) return PR_EINVAL;
+    int32_t mf = 0, mg = 0;
+    pr_status st = parareal_plan(grid, model, opt, &mf, &mg, nullptr, nullptr);
+    if (st != PR_OK) return st;
+    Req r;
+    r.id = sv->next_id++;
+    r.g = *grid;
+    r.m = *model;
+    r.p = *payoff;
+    r.o = *opt;
+    r.v_out = v_out;
+    r.bytes = pr_server_footprint(grid, opt);
+    if (r.bytes == 0) return PR_EINVAL;
+    if (r.bytes > sv->arena_bytes) return PR_ENOMEM;
+    r.t_submit = std::chrono::steady_clock::now();
+    *id_out = r.id;
+    sv->queue.push_back(r.id);
+    sv->reqs.emplace(r.id, r);
+    return PR_OK;
+}
+
+pr_status pr_server_progress(pr_server* sv, int32_t* n_resident, int32_t* n_queued,
+                             int32_t* n_done) {
+    if (!sv) return PR_EINVAL;
+    pr_status first_err = PR_OK;
+    // 1. advance requests whose in-flight work has finished
+    for (size_t i = 0; i < sv->resident.size();) {
+        Req& r = sv->reqs[sv->resident[i]];
+        const hipError_t q = hipEventQuery(r.ev);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        bool retire = false;
+        if (q != hipSuccess) {
+            r.status = PR_EDEVICE;
+            retire = true;
+        } else if (r.state == 1) {
+            // iteration done: enqueue the next one or the write of the result (state 2)
+            const pr_status st = req_advance(sv, r);
+            if (st != PR_OK) {
+                r.status = st;
+                retire = true;
+            }
+        } else {
+            retire = true;   // state 2: the result has been written
+        }
+        if (retire) {
+            if (r.status != PR_OK && r.status != PR_ENOTCONV && first_err == PR_OK)
+                first_err = r.status;
+            if (r.status != PR_OK && r.s) (void)hipStreamSynchronize(r.s->stream);
+            req_retire(sv, r);
+            sv->resident.erase(sv->resident.begin() + i);
+            continue;
+        }
+        ++i;
+    }
+    // 2. admit queued requests in order while they fit
+    while (!sv->queue.empty() && (int)sv->resident.size() < sv->max_resident) {
+        Req& r = sv->reqs[sv->queue.front()];
+        if (!arena_alloc(sv, r.bytes, &r.off)) break;
+        sv->queue.pop_front();
+        r.t_admit = std::chrono::steady_clock::now();
+        pr_status st = req_admit(sv, r);
+        sv->resident.push_back(r.id);
+        sv->peak_resident = std::max(sv->peak_resident, (int)sv->resident.size());
+        if (st != PR_OK) {
+            r.status = st;
+            if (first_err == PR_OK) first_err = st;
+            if (r.s) (void)hipStreamSynchronize(r.s->stream);
+            req_retire(sv, r);
+            sv->resident.pop_back();
+        }
+    }
+    if (n_resident) *n_resident = (int32_t)sv->resident.size();
+    if (n_queued) *n_queued = (int32_t)sv->queue.size();
+    if (n_done) *n_done = sv->n_done;
+    return first_err;
+}
+
+pr_status pr_server_poll(pr_server* sv, int64_t id, int32_t* done, pr_request_info* info) {
+    if (!sv || !done) return PR_EINVAL;
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return PR_EINVAL;
+    const Req& r = it->second;
+    *done = r.state == 3;
+    if (*done && info) {
+        info->status = r.status;
+        info->iters = r.k;
+        info->last_increment = r.inc;
+        info->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+        info->queue_ms = std::chrono::duration<double, std::milli>(r.t_admit - r.t_submit).count();
+        info->workspace_bytes = r.bytes;
+    }
+    return PR_OK;
+}
+
+pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t* peak_bytes) {
+    if (!sv) return PR_EINVAL;
+    if (peak_resident) *peak_resident = sv->peak_resident;
+    if (peak_bytes) *peak_bytes = sv->peak_bytes;
+    return PR_OK;
+}
+
+pr_status pr_server_destroy(pr_server* sv) {
+    if (!sv) return PR_EINVAL;
+    for (hipStream_t st : sv->streams) (void)hipStreamSynchronize(st);
+    for (int64_t id : sv->resident) {
+        Req& r = sv->reqs[id];
+        if (r.ev) (void)hipEventDestroy(r.ev);
+        if (r.s) parareal_destroy(r.s);
+    }
+    for (hipStream_t st : sv->streams) (void)hipStreamDestroy(st);
+    if (sv->pinned) (void)hipHostFree(sv->pinned);
+    delete sv;
+    return PR_OK;
+}
+
+}  // extern "C"
