@@ -97,11 +97,13 @@ def main():
 
     # correctness outside the timed region: error vs the GPU serial fine solution
     errs, iters, serial_ms = {s: float("nan") for s in seeds}, {s: 0 for s in seeds}, {s: 0.0 for s in seeds}
+    serial_ref = {}
     for s in ([] if args.no_check else seeds):
         sv = solvers[s]
         ser = sv.serial_fine()
         serial_ms[s] = ser.stats["t_total_ms"]
         ser_v = ser.value.clone()
+        serial_ref[s] = ser_v
         res = sv.solve()
         iters[s] = res.iters
         errs[s] = float((res.value - ser_v).abs().max() / ser_v.abs().max())
@@ -158,15 +160,61 @@ def main():
                      "correction": round(corr_ms, 2), "step_kernels": round(steps_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_fine_step<MODE_INCR> (FP32 increment step, 12 B/point)",
+                     "kernel": "k_fine_tb<MODE_INCR, S=4> (FP32 increment form, 4 explicit steps per launch, 12 B per point-step)",
                      "avg_launch_us": round(avg_launch_us, 3),
                      "bytes_per_launch": round(steps_bytes / max(1, steps_launch))},
     }
+    if not args.no_check:
+        out["lod_coarse"] = lod_leg(pr, insts, seeds, serial_ref)
+        out["serving"] = serving_leg(pr)
     if args.max_iters:
         out["note"] = "iterations capped at %d (counter run, not a bench line)" % args.max_iters
     if not args.no_cpu_baseline and not args.no_check:
         out["cpu_baseline"] = run_cpu_baseline(insts[0], iters[seeds[0]])
     print(json.dumps(out), flush=True)
+
+
+def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
+    """Same seeds with the same-grid implicit (LOD) coarse propagator, 4 steps per
+    slice: one warm solve, then one timed solve per seed."""
+    import torch
+    lat, iters, errs = [], [], []
+    for s, inst in zip(seeds, insts):
+        sv = pr.Solver(inst.replace(coarse_steps_per_slice=coarse_steps), coarse_kind=pr.PR_G_LOD)
+        sv.solve()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = sv.solve()
+        lat.append((time.perf_counter() - t) * 1e3)
+        iters.append(res.iters)
+        ref = serial_ref[s]
+        errs.append(float((res.value - ref).abs().max() / ref.abs().max()))
+        sv.close()
+    return {"workload": "same seeds, same-grid implicit coarse propagator (LOD, %d steps per "
+                        "slice) instead of the 129^2 explicit one" % coarse_steps,
+            "solves_per_s": round(len(lat) / (sum(lat) * 1e-3), 4),
+            "p50_ms": round(nearest_rank(lat, 50), 3), "p99_ms": round(nearest_rank(lat, 99), 3),
+            "iters": iters, "max_err_vs_serial_f": max(errs),
+            "parareal_ms": [round(x, 2) for x in lat]}
+
+
+def serving_leg(pr, rate=30.0, count=120, seed=11, sides=(129, 257)):
+    """Poisson arrivals of independent solves (seed-drawn parameters, T ~ U[0.25, 2],
+    N in {16, 32, 64}, grid side uniform over `sides`) through the continuous-batching
+    server with the same-grid implicit coarse propagator."""
+    import torch
+    from paper_2404_02521_amd.serve import Server, run_poisson
+    from synthetic import serving_requests
+    t, insts = serving_requests(rate, count, seed=seed, sides=sides)
+    sv = Server(64 << 30, max_resident=64, n_streams=8)
+    r = run_poisson(sv, t, insts)
+    sv.close()
+    torch.cuda.empty_cache()
+    return {"workload": "Poisson %.0f req/s, %d requests, sides %s, N in {16,32,64}, "
+                        "T~U[0.25,2]" % (rate, count, list(sides)),
+            "solves_per_s": round(r["solves_per_s"], 3), "p50_ms": round(r["p50_ms"], 2),
+            "p99_ms": round(r["p99_ms"], 2), "mean_iters": round(sum(r["iters"]) / count, 2),
+            "peak_resident": r["peak_resident"]}
 
 
 def run_cpu_baseline(inst, K_gpu):

@@ -232,7 +232,7 @@ StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, i
     StepArgs a = step_args(s, g, s->bcf, dt, first, count, step);
     const int W = kWave - 2 * S;
     a.nstrips = (g.nin + W - 1) / W;
-    long long target = 6144;
+    long long target = 5120;
     long long rows = (long long)g.nin * a.nstrips * count / target;
     rows = std::max<long long>(8, std::min<long long>(128, rows));
     if (s->rows_override > 0) rows = s->rows_override;
