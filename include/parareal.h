@@ -246,6 +246,104 @@ pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t*
 /* Blocks until all submitted work has drained, then releases the streams. */
 pr_status pr_server_destroy(pr_server* sv);
 
+/* ---------------------------------------------------------------------------
+ * Fourier neural operator (Sec. 3.4) and its training with a PDE-residual
+ * loss (Sec. 3.5).  Architecture: lift 7 -> 64 -> 32 with GELU, four Fourier
+ * layers of width 32 (truncated DFT to modes kx in {0..11, -12..-1},
+ * ky in {0..11}, a complex 32 x 32 multiplier per mode, inverse DFT, plus a
+ * pointwise 32 x 32 path and bias, GELU after all but the last), projection
+ * 32 -> 128 -> 1 with GELU, on a 64 x 64 grid.  GELU is the exact erf form.
+ *
+ * Per sample the input is one 64 x 64 plane w (x index major, y contiguous)
+ * and four parameters meta = (sigma1, sigma2, rho, r); the network sees the
+ * channels [w, sigma1, sigma2, rho, r, x/63, y/63] and returns one plane.
+ *
+ * Parameters are one flat FP32 vector of pr_fno_param_count() values, blocks
+ * in this order (row-major within a block, "in x out" for dense weights):
+ *   L1 (7,64) l1 (64) L2 (64,32) l2 (32),
+ *   per layer: Rr (24,12,32,32) Ri (24,12,32,32) W (32,32) b (32)
+ *              (multiplier of mode (kx index, ky) from input to output channel),
+ *   P1 (32,128) p1 (128) P2 (128,1) p2 (1).
+ *
+ * A training pair is four consecutive 64 x 64 FP32 planes
+ * [w_in, B1, V_in, V_tgt] (see pr_fno_loss).  The prediction of a pair is
+ * V1 = B1 + w_in + out_scale * out on the interior (the ring of the network's
+ * output is ignored), and its loss is the mean over the 62 x 62 interior of
+ * (V1 - V_tgt)^2 plus lam times the mean of R^2, where R is the discrete
+ * Crank-Nicolson residual (V1 - V_in) - dT L_h((V1 + V_in) / 2) of the
+ * operator of Eq. (fd) on the 64 x 64 grid (node (i, j) at index form i, j).
+ *
+ * Precision: PR_FNO_FP32 runs every contraction in FP32; PR_FNO_BF16 runs the
+ * channel contractions (lift, pointwise, per-mode multipliers, projection and
+ * their gradients) on bf16 matrix cores with FP32 accumulation, the DFTs in
+ * FP32.  Master weights, gradients and Adam moments are FP32.
+ *
+ * All buffers are device pointers unless marked host.  An FNO handle owns
+ * nothing but its caller-provided workspace (which holds the parameters,
+ * gradients, Adam moments and the activations of up to max_batch samples);
+ * its calls are enqueued on the stream given at create; a handle is used by
+ * one caller at a time.
+ * ------------------------------------------------------------------------- */
+#define PR_FNO_GRID 64
+#define PR_FNO_WIDTH 32
+#define PR_FNO_MODES 12
+#define PR_FNO_LAYERS 4
+#define PR_FNO_CIN 7
+#define PR_FNO_LIFT 64
+#define PR_FNO_PROJ 128
+#define PR_FNO_MAX_BATCH 512
+
+enum { PR_FNO_FP32 = 0, PR_FNO_BF16 = 1 };
+
+typedef struct pr_fno pr_fno; /* opaque */
+
+typedef struct {
+    int32_t max_batch;  /* samples per forward / training step, 1..PR_FNO_MAX_BATCH */
+    int32_t precision;  /* PR_FNO_*: precision of the inference a solver's coarse propagator runs */
+    double out_scale;   /* prediction = out_scale * network output, > 0 */
+} pr_fno_config;
+
+/* Number of FP32 parameters (host only). */
+uint64_t pr_fno_param_count(void);
+/* Workspace bytes for max_batch samples; 0 when out of range (host only). */
+uint64_t pr_fno_workspace_bytes(int32_t max_batch);
+/* Create; ws: device, 256-byte aligned, >= pr_fno_workspace_bytes(max_batch),
+ * borrowed until destroy.  Parameters start undefined: call pr_fno_set_params.
+ * Errors: PR_EINVAL (config), PR_ENOMEM (workspace too small), PR_EDEVICE. */
+pr_status pr_fno_create(const pr_fno_config* cfg, void* ws, uint64_t bytes, void* hip_stream,
+                        pr_fno** out);
+/* Copy the flat parameter vector in from / out to a device buffer; set also
+ * clears the Adam moments. */
+pr_status pr_fno_set_params(pr_fno* f, const float* src);
+pr_status pr_fno_get_params(pr_fno* f, float* dst);
+/* Copy the gradient vector of the last pr_fno_backward to a device buffer. */
+pr_status pr_fno_get_grads(pr_fno* f, float* dst);
+/* out (batch x 64 x 64) = network(w (batch x 64 x 64), meta (batch x 4)). */
+pr_status pr_fno_forward(pr_fno* f, const float* w, const float* meta, int32_t batch,
+                         int32_t precision, float* out);
+/* Gradients of sum(gout * out) with respect to the parameters, for the
+ * activations of the last pr_fno_forward (same batch and precision); the
+ * gradient vector is overwritten. */
+pr_status pr_fno_backward(pr_fno* f, const float* gout);
+/* Loss of batch pairs (batch x 4 x 64 x 64) against the prediction `pred`
+ * (batch x 64 x 64, scaled by `scale`); gpred (may be NULL) receives
+ * dLoss/dpred (zero on the ring); host_loss (host, may be NULL; the call then
+ * synchronises) receives [loss, data term, residual term]. */
+pr_status pr_fno_loss(pr_fno* f, const float* pred, const float* pairs, const float* meta,
+                      int32_t batch, double scale, double dT, double lam, float* gpred,
+                      double* host_loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the current
+ * gradients; step counts from 1. */
+pr_status pr_fno_adam(pr_fno* f, double lr, int32_t step);
+/* Forward, loss (scale = out_scale), backward and Adam on the pairs
+ * idx[0..batch) (device int32 indices into pairs (N x 4 x 64 x 64) and meta
+ * (N x 4)).  host_loss as in pr_fno_loss. */
+pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, const int32_t* idx,
+                            int32_t batch, double dT, double lam, double lr, int32_t step,
+                            int32_t precision, double* host_loss);
+pr_status pr_fno_destroy(pr_fno* f);
+const char* pr_fno_last_error(const pr_fno* f);
+
 const char* parareal_strerror(pr_status st);
 const char* parareal_last_error(const pr_solver* s);
 int32_t parareal_abi_version(void);

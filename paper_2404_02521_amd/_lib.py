@@ -22,6 +22,9 @@ PR_FP64, PR_FP32 = 0, 1
 PR_OP_FINE, PR_OP_COARSE = 0, 1
 PR_FLAG_TIME_STEPS = 1
 PR_FLAG_GRAPH = 2
+PR_FNO_FP32, PR_FNO_BF16 = 0, 1
+PR_FNO_GRID = 64
+PR_FNO_MAX_BATCH = 512
 
 
 class pr_grid(C.Structure):
@@ -61,6 +64,10 @@ class pr_server_options(C.Structure):
                 ("pad_", C.c_int32)]
 
 
+class pr_fno_config(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("precision", C.c_int32), ("out_scale", C.c_double)]
+
+
 class pr_request_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("last_increment", C.c_double),
                 ("latency_ms", C.c_double), ("queue_ms", C.c_double),
@@ -95,6 +102,25 @@ SIGNATURES = [
                                  C.POINTER(pr_request_info)]),
     ("pr_server_peaks", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
     ("pr_server_destroy", C.c_int, [C.c_void_p]),
+    ("pr_fno_param_count", C.c_uint64, []),
+    ("pr_fno_workspace_bytes", C.c_uint64, [C.c_int32]),
+    ("pr_fno_create", C.c_int, [C.POINTER(pr_fno_config), C.c_void_p, C.c_uint64, C.c_void_p,
+                                C.POINTER(C.c_void_p)]),
+    ("pr_fno_set_params", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pr_fno_get_params", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pr_fno_get_grads", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pr_fno_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                 C.c_void_p]),
+    ("pr_fno_backward", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("pr_fno_loss", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                              C.c_double, C.c_double, C.c_double, C.c_void_p,
+                              C.POINTER(C.c_double)]),
+    ("pr_fno_adam", C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
+    ("pr_fno_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                    C.POINTER(C.c_double)]),
+    ("pr_fno_destroy", C.c_int, [C.c_void_p]),
+    ("pr_fno_last_error", C.c_char_p, [C.c_void_p]),
 ]
 
 _lib = None

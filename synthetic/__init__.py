@@ -114,3 +114,45 @@ def serving_requests(rate: float, count: int, seed: int, sides=SERVE_SIDES):
         out.append(Instance(M=M, T=T, payoff=BASKET, n_slices=N, coarse_M=(M - 1) // 4 + 1,
                             cfl=0.9, fp32=True, tol=1e-7, tol_relative=True, **p))
     return t, out
+
+
+FNO_GRID = 64
+
+
+def fno_batch(seed: int, batch: int):
+    """Random inputs of the 64 x 64 neural operator: a plane w per sample (a few
+    random low sine modes plus small noise, zero on the ring) and the model
+    parameters (sigma1, sigma2, rho, r) drawn as in the at-scale problem.
+    Returns float32 arrays w (batch, 64, 64) and meta (batch, 4)."""
+    rng = np.random.default_rng(seed)
+    t = np.linspace(0.0, 1.0, FNO_GRID)
+    w = np.zeros((batch, FNO_GRID, FNO_GRID))
+    meta = np.zeros((batch, 4))
+    for b in range(batch):
+        p = draw_params(rng)
+        meta[b] = (p["sigma1"], p["sigma2"], p["rho"], p["r"])
+        for _ in range(4):
+            kx, ky = rng.integers(1, 9, size=2)
+            w[b] += rng.normal(0.0, 0.1) * np.outer(np.sin(np.pi * kx * t), np.sin(np.pi * ky * t))
+        w[b, 1:-1, 1:-1] += rng.normal(0.0, 0.01, size=(FNO_GRID - 2, FNO_GRID - 2))
+        w[b, [0, -1], :] = 0.0
+        w[b, :, [0, -1]] = 0.0
+    return w.astype(np.float32), meta.astype(np.float32)
+
+
+def fno_pairs(seed: int, batch: int):
+    """Random training pairs [w_in, B1, V_in, V_tgt] (batch, 4, 64, 64) float32 with
+    the magnitudes of option values on [0, 4]^2 (a smooth ramp plus the random
+    planes of fno_batch), and their meta (batch, 4)."""
+    w, meta = fno_batch(seed, batch)
+    rng = np.random.default_rng(seed + 7919)
+    x = np.linspace(0.0, 4.0, FNO_GRID)
+    ramp = 0.5 * (x[:, None] + x[None, :])
+    pairs = np.zeros((batch, 4, FNO_GRID, FNO_GRID))
+    for b in range(batch):
+        a0 = rng.uniform(0.9, 1.1)
+        pairs[b, 0] = w[b]
+        pairs[b, 1] = a0 * ramp
+        pairs[b, 2] = 0.99 * a0 * ramp + w[b]
+        pairs[b, 3] = a0 * ramp + w[b] + rng.normal(0.0, 1e-3, size=(FNO_GRID, FNO_GRID))
+    return pairs.astype(np.float32), meta

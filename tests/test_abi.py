@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "parareal.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:parareal|pr_server)_\w+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b((?:parareal|pr_server|pr_fno)_\w+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -35,7 +35,8 @@ def test_struct_layouts_match_header(tmp_path):
     """sizeof / offsetof from the C compiler against the ctypes mirrors."""
     structs = {"pr_grid": L.pr_grid, "pr_model": L.pr_model, "pr_payoff": L.pr_payoff,
                "pr_options": L.pr_options, "pr_stats": L.pr_stats,
-               "pr_server_options": L.pr_server_options, "pr_request_info": L.pr_request_info}
+               "pr_server_options": L.pr_server_options, "pr_request_info": L.pr_request_info,
+               "pr_fno_config": L.pr_fno_config}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){']
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} %zu\\n", sizeof({sname}));')
