@@ -70,6 +70,15 @@ enum { PR_BC_FORWARD_INTRINSIC = 0, /* basket: max(w1 S1 + w2 S2 - K e^{-r tau},
 
 /* Coarse propagator. */
 enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilinear */
+       PR_G_FNO = 1,       /* the Fourier neural operator of Sec. 3.4 on a 64 x 64 grid, reached
+                              through sine (DST-I) transfers of V - B(tau), B the Coons patch of
+                              the ring values: G(u) = B(tau_{n+1}) + P_s(w + out_scale *
+                              FNO(w, sigma1, sigma2, rho, r)), w = R_s(u - B(tau_n)), with w
+                              replaced by the base of the operator's PR_FNO_BASE_*.  Needs
+                              n >= 64 and an operator attached with parareal_attach_fno.  If the
+                              increment is non-finite or grows in two consecutive iterations, the
+                              solve restarts with PR_G_LOD (coarse_steps, default 4) and reports
+                              pr_stats.coarse_fallback = 1; the solver keeps PR_G_LOD after that */
        PR_G_FINE = 2,      /* G := F (test mode: Parareal stops after one iteration) */
        PR_G_LOD = 3        /* implicit Euler on the fine grid with coarse_steps steps per
                               slice (default 2), split by direction: the explicit mixed
@@ -87,6 +96,10 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
  * cached per k and reused by later solves of the same solver.  Phase timings
  * then cover whole iterations (t_fine_ms) and PR_FLAG_TIME_STEPS is ignored. */
 #define PR_FLAG_GRAPH 2u
+/* PR_FLAG_NO_FALLBACK: PR_G_FNO keeps the neural propagator even when the
+ * increments grow (a non-finite increment then ends the solve with
+ * PR_ENONFINITE, as for the other propagators). */
+#define PR_FLAG_NO_FALLBACK 4u
 
 /* Arithmetic of the fine and numerical coarse propagators. */
 enum { PR_FP64 = 0, /* everything in FP64 */
@@ -144,6 +157,8 @@ typedef struct {
     double fine_step_bytes;     /* algorithmic bytes moved by those launches */
     double t_step_kernels_ms;   /* GPU time of those launches (HIP events, see PR_FLAG_TIME_STEPS) */
     uint64_t workspace_bytes;   /* bytes of workspace the solver uses */
+    int32_t coarse_fallback;    /* 1 when PR_G_FNO fell back to PR_G_LOD in this solve */
+    int32_t pad_;
 } pr_stats;
 
 /* Explicit-Euler stability bound and the planned step counts (host only, no
@@ -189,6 +204,27 @@ enum { PR_OP_FINE = 0, PR_OP_COARSE = 1 };
 pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* in, double* out);
 
 pr_status parareal_destroy(pr_solver* s);
+
+/* PR_G_FNO solvers: attach the operator (borrowed, not owned; it must outlive
+ * the solver's use of it and is used on the solver's stream, one solve at a
+ * time).  PR_EINVAL for solvers of another coarse kind. */
+typedef struct pr_fno pr_fno;
+pr_status parareal_attach_fno(pr_solver* s, pr_fno* f);
+
+/* PR_G_FNO solvers: one training pair of the operator from two fine states,
+ * v0 at tau_slice and v1 at tau_{slice+1} (n*n doubles each, device).  Writes
+ * four 64 x 64 FP32 planes (device) [w_in, B1, V_in, V_tgt]: w_in = R_s(v0 -
+ * B(tau_slice)) with zero ring, B1 = the Coons patch of g(tau_{slice+1}) on the
+ * 64 x 64 grid (base PR_FNO_BASE_LOD: plus the LOD prediction's w), V_in =
+ * B0 + w_in and V_tgt = B1 + R_s(v1 - B(tau_{slice+1})) with the Coons B1. */
+pr_status parareal_fno_pair(pr_solver* s, int32_t slice, const double* v0, const double* v1,
+                            int32_t base, float* pair_out);
+
+/* PR_G_FNO solvers: the training pairs of one whole trajectory.  Runs serial F
+ * from the payoff over all N slices and writes, for every slice n, the pair of
+ * parareal_fno_pair from the F states at tau_n and tau_{n+1}: pairs_out
+ * (device) receives N x 4 x 64 x 64 floats. */
+pr_status parareal_fno_pairs(pr_solver* s, int32_t base, float* pairs_out);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent Parareal solves (no counterpart
@@ -267,8 +303,10 @@ pr_status pr_server_destroy(pr_server* sv);
  *
  * A training pair is four consecutive 64 x 64 FP32 planes
  * [w_in, B1, V_in, V_tgt] (see pr_fno_loss).  The prediction of a pair is
- * V1 = B1 + w_in + out_scale * out on the interior (the ring of the network's
- * output is ignored), and its loss is the mean over the 62 x 62 interior of
+ * V1 = B1 + w_in + out_scale * out (base PR_FNO_BASE_IDENTITY) or
+ * V1 = B1 + out_scale * out (the other bases; with PR_FNO_BASE_LOD the pair's
+ * B1 plane carries the LOD prediction) on the interior (the ring of the
+ * network's output is ignored), and its loss is the mean over the 62 x 62 interior of
  * (V1 - V_tgt)^2 plus lam times the mean of R^2, where R is the discrete
  * Crank-Nicolson residual (V1 - V_in) - dT L_h((V1 + V_in) / 2) of the
  * operator of Eq. (fd) on the 64 x 64 grid (node (i, j) at index form i, j).
@@ -295,12 +333,23 @@ pr_status pr_server_destroy(pr_server* sv);
 
 enum { PR_FNO_FP32 = 0, PR_FNO_BF16 = 1 };
 
-typedef struct pr_fno pr_fno; /* opaque */
+/* What the network's (scaled) output is added to, on the 62 x 62 interior of
+ * the operator grid, to give the restricted state after the slice:
+ *   PR_FNO_BASE_ZERO     nothing: the network predicts the new w;
+ *   PR_FNO_BASE_IDENTITY w_in: the network predicts the change of w;
+ *   PR_FNO_BASE_LOD      the LOD implicit propagator (PR_G_LOD's scheme) run on
+ *                        the 64 x 64 grid itself over the slice (coarse_steps
+ *                        steps, default 4) from B(tau_n) + w_in: the network
+ *                        predicts the correction to that cheap, stable step. */
+enum { PR_FNO_BASE_ZERO = 0, PR_FNO_BASE_IDENTITY = 1, PR_FNO_BASE_LOD = 2 };
+
 
 typedef struct {
-    int32_t max_batch;  /* samples per forward / training step, 1..PR_FNO_MAX_BATCH */
-    int32_t precision;  /* PR_FNO_*: precision of the inference a solver's coarse propagator runs */
-    double out_scale;   /* prediction = out_scale * network output, > 0 */
+    int32_t max_batch;      /* samples per forward / training step, 1..PR_FNO_MAX_BATCH */
+    int32_t precision;      /* PR_FNO_*: precision of the inference a solver's coarse propagator runs */
+    double out_scale;       /* prediction = out_scale * network output, > 0 */
+    int32_t base;           /* PR_FNO_BASE_*: what the prediction is added to */
+    int32_t pad_;
 } pr_fno_config;
 
 /* Number of FP32 parameters (host only). */
@@ -326,7 +375,8 @@ pr_status pr_fno_forward(pr_fno* f, const float* w, const float* meta, int32_t b
  * gradient vector is overwritten. */
 pr_status pr_fno_backward(pr_fno* f, const float* gout);
 /* Loss of batch pairs (batch x 4 x 64 x 64) against the prediction `pred`
- * (batch x 64 x 64, scaled by `scale`); gpred (may be NULL) receives
+ * (batch x 64 x 64, scaled by `scale`, added to w_in when the handle's base
+ * is PR_FNO_BASE_IDENTITY); gpred (may be NULL) receives
  * dLoss/dpred (zero on the ring); host_loss (host, may be NULL; the call then
  * synchronises) receives [loss, data term, residual term]. */
 pr_status pr_fno_loss(pr_fno* f, const float* pred, const float* pairs, const float* meta,

@@ -17,12 +17,14 @@ PR_MAX_SLICES = 1024
 PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_ENOTCONV, PR_ENONFINITE, PR_EMODEL = range(8)
 PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE = 0, 1
 PR_BC_FORWARD_INTRINSIC, PR_BC_DISCOUNTED_PAYOFF, PR_BC_EXACT = 0, 1, 2
-PR_G_NUMERICAL, PR_G_FINE, PR_G_LOD = 0, 2, 3
+PR_G_NUMERICAL, PR_G_FNO, PR_G_FINE, PR_G_LOD = 0, 1, 2, 3
 PR_FP64, PR_FP32 = 0, 1
 PR_OP_FINE, PR_OP_COARSE = 0, 1
 PR_FLAG_TIME_STEPS = 1
 PR_FLAG_GRAPH = 2
+PR_FLAG_NO_FALLBACK = 4
 PR_FNO_FP32, PR_FNO_BF16 = 0, 1
+PR_FNO_BASE_ZERO, PR_FNO_BASE_IDENTITY, PR_FNO_BASE_LOD = 0, 1, 2
 PR_FNO_GRID = 64
 PR_FNO_MAX_BATCH = 512
 
@@ -56,7 +58,8 @@ class pr_stats(C.Structure):
                 ("t_chain_ms", C.c_double), ("t_correct_ms", C.c_double),
                 ("fine_point_steps", C.c_int64), ("fine_step_launches", C.c_int64),
                 ("fine_step_bytes", C.c_double), ("t_step_kernels_ms", C.c_double),
-                ("workspace_bytes", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("coarse_fallback", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class pr_server_options(C.Structure):
@@ -65,7 +68,8 @@ class pr_server_options(C.Structure):
 
 
 class pr_fno_config(C.Structure):
-    _fields_ = [("max_batch", C.c_int32), ("precision", C.c_int32), ("out_scale", C.c_double)]
+    _fields_ = [("max_batch", C.c_int32), ("precision", C.c_int32), ("out_scale", C.c_double),
+                ("base", C.c_int32), ("pad_", C.c_int32)]
 
 
 class pr_request_info(C.Structure):
@@ -87,6 +91,10 @@ SIGNATURES = [
     ("parareal_serial_fine", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(pr_stats)]),
     ("parareal_apply", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     ("parareal_destroy", C.c_int, [C.c_void_p]),
+    ("parareal_attach_fno", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("parareal_fno_pair", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                     C.c_void_p]),
+    ("parareal_fno_pairs", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("parareal_strerror", C.c_char_p, [C.c_int]),
     ("parareal_last_error", C.c_char_p, [C.c_void_p]),
     ("parareal_abi_version", C.c_int32, []),

@@ -338,12 +338,13 @@ struct LossArgs {
     double* part;
     int B;
     double scale, dT, lam;
+    double skip;   // 1: the prediction is a change of w_in, 0: the new w
 };
 
 __device__ inline double v1_at(const LossArgs& a, const float* pr, const float* ob, int x, int y) {
     const int p = x * G + y;
     const bool in = x > 0 && x < G - 1 && y > 0 && y < G - 1;
-    return (double)pr[GG + p] + (double)pr[p] + (in ? a.scale * (double)ob[p] : 0.0);
+    return (double)pr[GG + p] + a.skip * (double)pr[p] + (in ? a.scale * (double)ob[p] : 0.0);
 }
 
 __global__ __launch_bounds__(64) void k_loss1(LossArgs a) {
@@ -594,6 +595,8 @@ struct pr_fno {
     int fwd_prec = 0;       // precision of the last forward
     int infer_prec = 0;     // precision of the coarse-propagator inference
     double out_scale = 1.0;
+    int base = PR_FNO_BASE_IDENTITY;
+    double skip = 1.0;      // 1 when the prediction is a change of w_in
     std::string err;
     template <typename T = float>
     T* at(uint64_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -885,7 +888,7 @@ hipError_t backward(pr_fno* f, const float* gout, int B, bool mf) {
 hipError_t loss(pr_fno* f, const float* out, const float* pairs, const float* meta, const int* idx,
                 int B, double scale, double dT, double lam) {
     LossArgs a{out, pairs, meta, idx, f->at(f->L.gpred), f->at(f->L.cc),
-               f->at<double>(f->L.lpart), B, scale, dT, lam};
+               f->at<double>(f->L.lpart), B, scale, dT, lam, f->skip};
     hipLaunchKernelGGL(k_loss1, dim3(B * G), dim3(64), 0, f->st, a);
     hipLaunchKernelGGL(k_loss2, dim3(B * G), dim3(64), 0, f->st, a);
     hipLaunchKernelGGL(k_loss3, dim3(1), dim3(256), 0, f->st, f->at<double>(f->L.lpart), B * G,
@@ -920,6 +923,7 @@ hipError_t infer(pr_fno* f, const float* w, const float* meta, int B, float* out
 }
 int max_batch(const pr_fno* f) { return f->Bm; }
 double out_scale(const pr_fno* f) { return f->out_scale; }
+int base(const pr_fno* f) { return f->base; }
 
 hipError_t gemm_f64(const double* A, long long ars, long long acs, const double* B, long long brs,
                     long long bcs, double* Cp, long long crs, int M, int N, int K, double beta,
@@ -947,6 +951,7 @@ pr_status pr_fno_create(const pr_fno_config* cfg, void* ws, uint64_t bytes, void
     if (!cfg || cfg->max_batch < 1 || cfg->max_batch > PR_FNO_MAX_BATCH) return PR_EINVAL;
     if (!valid_prec(cfg->precision)) return PR_EINVAL;
     if (!(cfg->out_scale > 0.0) || !std::isfinite(cfg->out_scale)) return PR_EINVAL;
+    if (cfg->base < PR_FNO_BASE_ZERO || cfg->base > PR_FNO_BASE_LOD) return PR_EINVAL;
     const Layout L = make_layout(cfg->max_batch);
     if (!ws || bytes < L.total) return PR_ENOMEM;
     if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return PR_EINVAL;
@@ -960,6 +965,8 @@ pr_status pr_fno_create(const pr_fno_config* cfg, void* ws, uint64_t bytes, void
     f->grads = f->at(L.grads);
     f->infer_prec = cfg->precision;
     f->out_scale = cfg->out_scale;
+    f->base = cfg->base;
+    f->skip = cfg->base == PR_FNO_BASE_IDENTITY ? 1.0 : 0.0;
     float* tabs = f->at(L.tabs);
     f->EyF = tabs;
     f->ExF = f->EyF + 2 * MX * G;

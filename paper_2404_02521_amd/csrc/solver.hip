@@ -44,6 +44,21 @@ hipError_t launch_finalize(const double*, const float*, double*, const Grid&, hi
 hipError_t launch_lod_slice(const double*, double*, double*, double*, double*, const Grid&,
                             const Coef&, const Bc&, double, double, int, hipStream_t);
 hipError_t lod_set_lds(int);
+hipError_t launch_lift(const double*, double*, const Grid&, const Bc&, double, double, hipStream_t);
+hipError_t launch_fno_in(const double*, float*, float*, const Bc&, hipStream_t);
+hipError_t launch_fno_out(const double*, const float*, double, double*, hipStream_t);
+hipError_t launch_pair(const double*, const double*, const double*, float*, const Bc&, double,
+                       double, double, hipStream_t);
+void sine_transfer_matrices(int nf, std::vector<double>& R, std::vector<double>& P);
+namespace fno {
+hipError_t infer(pr_fno* f, const float* w, const float* meta, int B, float* out, hipStream_t st);
+double out_scale(const pr_fno* f);
+int base(const pr_fno* f);
+hipError_t gemm_f64(const double* A, long long ars, long long acs, const double* B, long long brs,
+                    long long bcs, double* C, long long crs, int M, int N, int K, double beta,
+                    hipStream_t st);
+}  // namespace fno
+constexpr int kFnoInt = 62;   // interior nodes per side of the 64 x 64 operator grid
 }  // namespace pr
 
 using namespace pr;
@@ -86,7 +101,8 @@ double gershgorin_dt(int n, const pr_model& m) {
 
 struct Layout {
     uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
-        lw0, lw1, lwb, total;
+        lw0, lw1, lwb, Sr, Sp, fwf, fT, fwc, fwc1, fTp, fin, fmeta, fout, fvc0, fvc1, flw0, flw1,
+        flwb, fwb, total;
 };
 
 bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
@@ -97,8 +113,10 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
     if (o->n_slices < 1 || o->n_slices > PR_MAX_SLICES) return fail("n_slices out of range");
     if (o->precision != PR_FP64 && o->precision != PR_FP32) return fail("unknown precision");
     if (o->coarse_kind != PR_G_NUMERICAL && o->coarse_kind != PR_G_FINE &&
-        o->coarse_kind != PR_G_LOD)
+        o->coarse_kind != PR_G_LOD && o->coarse_kind != PR_G_FNO)
         return fail("unknown coarse_kind");
+    if (o->coarse_kind == PR_G_FNO && g->n < 64)
+        return fail("PR_G_FNO needs at least 64 nodes per side");
     if (o->coarse_kind == PR_G_NUMERICAL) {
         if (o->coarse_n < 3) return fail("coarse_n must be >= 3");
         if ((g->n - 1) % (o->coarse_n - 1) != 0)
@@ -124,7 +142,8 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     const bool fp32 = o->precision == PR_FP32;
     const bool gfine = o->coarse_kind == PR_G_FINE;
     const bool lod = o->coarse_kind == PR_G_LOD;
-    const bool fineg = gfine || lod;   // G runs on the fine grid (chain over fine slices)
+    const bool fno = o->coarse_kind == PR_G_FNO;
+    const bool fineg = gfine || lod || fno;   // G returns fine-grid states (chain over fine slices)
     const uint64_t nc = fineg ? 0 : (uint64_t)o->coarse_n;
     Layout L{};
     uint64_t p = 0;
@@ -147,9 +166,26 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.twA = take(gfine && !fp32 ? sd : 0);
     L.twB = take(gfine && !fp32 ? sd : 0);
     L.tg = take(fineg ? sd : 0);
-    L.lw0 = take(lod ? sd : 0);
-    L.lw1 = take(lod ? sd : 0);
-    L.lwb = take(lod ? sd : 0);
+    L.lw0 = take(lod || fno ? sd : 0);   // PR_G_FNO falls back to LOD
+    L.lw1 = take(lod || fno ? sd : 0);
+    L.lwb = take(lod || fno ? sd : 0);
+    const uint64_t nf = fg.nin, mi = kFnoInt;
+    L.Sr = take(fno ? mi * nf * 8 : 0);
+    L.Sp = take(fno ? nf * mi * 8 : 0);
+    L.fwf = take(fno ? sd : 0);
+    L.fT = take(fno ? mi * nf * 8 : 0);
+    L.fwc = take(fno ? mi * mi * 8 : 0);
+    L.fwc1 = take(fno ? mi * mi * 8 : 0);
+    L.fTp = take(fno ? nf * mi * 8 : 0);
+    L.fin = take(fno ? 64 * 64 * 4 : 0);
+    L.fmeta = take(fno ? 16 : 0);
+    L.fout = take(fno ? 64 * 64 * 4 : 0);
+    L.fvc0 = take(fno ? mi * mi * 8 : 0);   // PR_FNO_BASE_LOD: the 64 x 64 grid's own states
+    L.fvc1 = take(fno ? mi * mi * 8 : 0);
+    L.flw0 = take(fno ? mi * mi * 8 : 0);
+    L.flw1 = take(fno ? mi * mi * 8 : 0);
+    L.flwb = take(fno ? mi * mi * 8 : 0);
+    L.fwb = take(fno ? mi * mi * 8 : 0);
     L.red = take(64);
     L.total = p;
     return L;
@@ -168,7 +204,8 @@ struct pr_solver {
     Bc bcf{}, bcc{};
     int N = 0, nc = 0, q = 1, mF = 0, mG = 0, maxit = 0;
     double dT = 0, dtF = 0, dtG = 0, ring_max_T = 0;
-    bool fp32 = false, fineg = false, lod = false;
+    bool fp32 = false, fineg = false, lod = false, fnog = false;
+    pr_fno* fno = nullptr;             // PR_G_FNO: the attached operator (borrowed)
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
     Layout L{};
@@ -403,8 +440,72 @@ pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
     return PR_OK;
 }
 
-// The G = F chain for slice n: g = F(U^{k+1}_n) into tg (one slice).
+// R_s: fine interior state u at tau (interior layout) -> 62 x 62 coefficients
+// field wc on the operator grid: wc = Sr (u - B(tau)) Sr^T.
+pr_status fno_restrict(pr_solver* s, const double* u, double tau, double* wc) {
+    const Grid& g = s->fg;
+    const int nf = g.nin, mi = kFnoInt;
+    double* wf = s->at<double>(s->L.fwf);
+    double* T = s->at<double>(s->L.fT);
+    const double* Sr = s->at<double>(s->L.Sr);
+    HIPCHK(launch_lift(u, wf, g, s->bcf, tau, -1.0, s->stream));
+    HIPCHK(fno::gemm_f64(Sr, nf, 1, wf, g.pitch, 1, T, nf, mi, nf, nf, 0.0, s->stream));
+    HIPCHK(fno::gemm_f64(T, nf, 1, Sr, 1, nf, wc, mi, mi, mi, nf, 0.0, s->stream));
+    return PR_OK;
+}
+
+// PR_FNO_BASE_LOD: the LOD propagator on the 64 x 64 grid itself over slice n
+// from B(tau_n) + wc; wb = its result minus B(tau_{n+1}) (62 x 62 interior).
+pr_status fno_lod_base(pr_solver* s, const double* wc, int n, double* wb) {
+    const int mi = kFnoInt;
+    const Grid g64{64, mi, mi, (long long)mi * mi};
+    Bc bc = s->bcf;
+    bc.h = s->grid.s_max / 63.0;
+    const int m = s->opt.coarse_steps > 0 ? s->opt.coarse_steps : 4;
+    double* v0 = s->at<double>(s->L.fvc0);
+    double* v1 = s->at<double>(s->L.fvc1);
+    HIPCHK(launch_lift(wc, v0, g64, bc, n * s->dT, 1.0, s->stream));
+    HIPCHK(launch_lod_slice(v0, v1, s->at<double>(s->L.flw0), s->at<double>(s->L.flw1),
+                            s->at<double>(s->L.flwb), g64, s->coef, bc, s->dT / m, n * s->dT, m,
+                            s->stream));
+    HIPCHK(launch_lift(v1, wb, g64, bc, (n + 1) * s->dT, -1.0, s->stream));
+    return PR_OK;
+}
+
+// Neural G over slice n: gout = B(tau_{n+1}) + P_s(base + scale * FNO(wc, params)),
+// wc = R_s(U_n); the ring of gout is g(tau_{n+1}) by construction of B.
+pr_status fno_g(pr_solver* s, const double* Uall, int n, double* gout) {
+    const Grid& g = s->fg;
+    const int nf = g.nin, mi = kFnoInt;
+    double* wc = s->at<double>(s->L.fwc);
+    double* wo = s->at<double>(s->L.fwc1);
+    double* Tp = s->at<double>(s->L.fTp);
+    const double* Sp = s->at<double>(s->L.Sp);
+    pr_status r = fno_restrict(s, Uall + (long long)n * g.stride, n * s->dT, wc);
+    if (r != PR_OK) return r;
+    float* fin = s->at<float>(s->L.fin);
+    float* fmeta = s->at<float>(s->L.fmeta);
+    float* fout = s->at<float>(s->L.fout);
+    HIPCHK(launch_fno_in(wc, fin, fmeta, s->bcf, s->stream));
+    HIPCHK(fno::infer(s->fno, fin, fmeta, 1, fout, s->stream));
+    const double* base = nullptr;
+    if (fno::base(s->fno) == PR_FNO_BASE_IDENTITY) base = wc;
+    if (fno::base(s->fno) == PR_FNO_BASE_LOD) {
+        double* wb = s->at<double>(s->L.fwb);
+        r = fno_lod_base(s, wc, n, wb);
+        if (r != PR_OK) return r;
+        base = wb;
+    }
+    HIPCHK(launch_fno_out(base, fout, fno::out_scale(s->fno), wo, s->stream));
+    HIPCHK(fno::gemm_f64(Sp, mi, 1, wo, mi, 1, Tp, mi, nf, mi, mi, 0.0, s->stream));
+    HIPCHK(fno::gemm_f64(Tp, mi, 1, Sp, 1, mi, gout, g.pitch, nf, nf, mi, 0.0, s->stream));
+    HIPCHK(launch_lift(gout, gout, g, s->bcf, (n + 1) * s->dT, 1.0, s->stream));
+    return PR_OK;
+}
+
+// The fine-grid G over slice n: g = G(U^{k+1}_n) into gout (one slice).
 pr_status fine_g(pr_solver* s, const double* Uslice_base_all, int n, double* gout) {
+    if (s->fnog) return fno_g(s, Uslice_base_all, n, gout);
     if (s->lod) {
         HIPCHK(launch_lod_slice(Uslice_base_all + (long long)n * s->fg.stride, gout,
                                 s->at<double>(s->L.lw0), s->at<double>(s->L.lw1),
@@ -527,9 +628,29 @@ pr_status run_phase(pr_solver* s, int key, Fn&& fn) {
     return PR_OK;
 }
 
+// PR_G_FNO fallback: the same-grid LOD propagator with the given (or 4)
+// coarse steps per slice; cached graphs of the neural G are dropped.
+pr_status switch_to_lod(pr_solver* s) {
+    s->fnog = false;
+    s->lod = true;
+    s->mG = s->opt.coarse_steps > 0 ? s->opt.coarse_steps : 4;
+    s->dtG = s->dT / s->mG;
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->graph_defs) (void)hipGraphDestroy(kv.second);
+    s->graphs.clear();
+    s->graph_defs.clear();
+    HIPCHK(lod_set_lds(s->fg.nin));
+    return PR_OK;
+}
+
 pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
     const Grid& g = s->fg;
     const int N = s->N;
+    if (s->fnog && !s->fno) {
+        s->err = "PR_G_FNO solver without an attached operator (parareal_attach_fno)";
+        return PR_EMODEL;
+    }
+    bool diverging = false;   // PR_G_FNO: non-finite, or two increments in a row growing
     double* Ucur = s->U(0);
     double* Unext = s->U(1);
     double t_fine = 0, t_chain = 0, t_corr = 0, t_steps = 0, step_bytes = 0;
@@ -546,6 +667,7 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
     int K = 0;
     pr_status status = PR_OK;
     double inc = 0, scale = 0;
+    double st_prev[2] = {0.0, 0.0};
     for (int k = 0; k < s->maxit && k < N; ++k) {
         // ---- F sweep over active slices k..N-1, chain, correction + norm
         s->sweep_launches = 0;
@@ -583,6 +705,13 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
         scale = std::max(scint, s->ring_max_T);
         K = k + 1;
         if (st && k <= PR_MAX_SLICES) st->increments[k] = inc;
+        if (s->fnog && !(s->opt.flags & PR_FLAG_NO_FALLBACK) &&
+            (hred[2] || (k >= 2 && inc > st_prev[1] && st_prev[1] > st_prev[0]))) {
+            diverging = true;
+            break;
+        }
+        st_prev[0] = st_prev[1];
+        st_prev[1] = inc;
         if (hred[2]) {
             status = PR_ENONFINITE;
             s->err = "non-finite value in the Parareal iteration";
@@ -594,6 +723,13 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
             status = PR_ENOTCONV;
             s->err = "max_iters reached above tolerance";
         }
+    }
+    if (diverging) {
+        pr_status r = switch_to_lod(s);
+        if (r != PR_OK) return r;
+        r = do_solve(s, v_out, st);
+        if (st) st->coarse_fallback = 1;
+        return r;
     }
     if (v_out) HIPCHK(launch_unpack(Ucur + (long long)N * g.stride, v_out, g, s->bcf, N * s->dT, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -703,7 +839,8 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     s->maxit = opt->max_iters > 0 ? std::min(opt->max_iters, s->N) : s->N;
     s->fp32 = opt->precision == PR_FP32;
     s->lod = opt->coarse_kind == PR_G_LOD;
-    s->fineg = opt->coarse_kind == PR_G_FINE || s->lod;
+    s->fnog = opt->coarse_kind == PR_G_FNO;
+    s->fineg = opt->coarse_kind == PR_G_FINE || s->lod || s->fnog;
     s->nc = s->fineg ? 0 : opt->coarse_n;
     s->q = s->fineg ? 1 : (grid->n - 1) / (opt->coarse_n - 1);
     s->mF = mf;
@@ -743,6 +880,20 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     if (s->lod && lod_set_lds(s->fg.nin) != hipSuccess) {
         delete s;
         return PR_EDEVICE;
+    }
+    if (s->fnog) {
+        std::vector<double> R, P;
+        sine_transfer_matrices(s->fg.nin, R, P);
+        hipError_t e = hipMemcpyAsync(s->at<double>(L.Sr), R.data(), R.size() * 8,
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s->at<double>(L.Sp), P.data(), P.size() * 8, hipMemcpyHostToDevice,
+                               s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) {
+            delete s;
+            return PR_EDEVICE;
+        }
     }
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
@@ -833,6 +984,10 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
                                  w ? w + (long long)slice * g.stride : nullptr, Us1);
         if (r != PR_OK) return r;
     } else if (s->fineg) {
+        if (s->fnog && !s->fno) {
+            s->err = "PR_G_FNO solver without an attached operator (parareal_attach_fno)";
+            return PR_EMODEL;
+        }
         pr_status r = fine_g(s, U, slice, Us1);
         if (r != PR_OK) return r;
     } else {
@@ -843,6 +998,95 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
                               s->stream));
     }
     HIPCHK(launch_unpack(Us1, out, g, s->bcf, (slice + 1) * s->dT, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PR_OK;
+}
+
+pr_status parareal_attach_fno(pr_solver* s, pr_fno* f) {
+    if (!s || !f) return PR_EINVAL;
+    if (s->opt.coarse_kind != PR_G_FNO) {
+        s->err = "the solver was not created with PR_G_FNO";
+        return PR_EINVAL;
+    }
+    s->fno = f;
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->graph_defs) (void)hipGraphDestroy(kv.second);
+    s->graphs.clear();
+    s->graph_defs.clear();
+    return PR_OK;
+}
+
+pr_status parareal_fno_pair(pr_solver* s, int32_t slice, const double* v0, const double* v1,
+                            int32_t base, float* pair_out) {
+    if (!s || !v0 || !v1 || !pair_out) return PR_EINVAL;
+    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_LOD) return PR_EINVAL;
+    if (s->opt.coarse_kind != PR_G_FNO) {
+        s->err = "the solver was not created with PR_G_FNO";
+        return PR_EINVAL;
+    }
+    if (slice < 0 || slice >= s->N) return PR_EINVAL;
+    const Grid& g = s->fg;
+    double* u = s->at<double>(s->L.tg);
+    double* w0 = s->at<double>(s->L.fwc);
+    double* w1 = s->at<double>(s->L.fwc1);
+    HIPCHK(launch_pack(v0, u, g, s->stream));
+    pr_status r = fno_restrict(s, u, slice * s->dT, w0);
+    if (r != PR_OK) return r;
+    HIPCHK(launch_pack(v1, u, g, s->stream));
+    r = fno_restrict(s, u, (slice + 1) * s->dT, w1);
+    if (r != PR_OK) return r;
+    double* wb = nullptr;
+    if (base == PR_FNO_BASE_LOD) {
+        wb = s->at<double>(s->L.fwb);
+        r = fno_lod_base(s, w0, slice, wb);
+        if (r != PR_OK) return r;
+    }
+    HIPCHK(launch_pair(w0, w1, wb, pair_out, s->bcf, s->grid.s_max, slice * s->dT,
+                       (slice + 1) * s->dT, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return PR_OK;
+}
+
+pr_status parareal_fno_pairs(pr_solver* s, int32_t base, float* pairs_out) {
+    if (!s || !pairs_out) return PR_EINVAL;
+    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_LOD) return PR_EINVAL;
+    if (s->opt.coarse_kind != PR_G_FNO) {
+        s->err = "the solver was not created with PR_G_FNO";
+        return PR_EINVAL;
+    }
+    const Grid& g = s->fg;
+    double* U = s->U(0);
+    s->sweep_launches = 0;
+    s->sweep_bytes = 0;
+    HIPCHK(launch_payoff(U, g, s->bcf, s->stream));
+    for (int n = 0; n < s->N; ++n) {   // serial F, every slice state kept
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, U, n, 1, false, &d, &w, nullptr);
+        if (r != PR_OK) return r;
+        r = fine_result_to_state(s, U + (long long)n * g.stride,
+                                 d ? d + (long long)n * g.stride : nullptr,
+                                 w ? w + (long long)n * g.stride : nullptr,
+                                 U + (long long)(n + 1) * g.stride);
+        if (r != PR_OK) return r;
+    }
+    double* w0 = s->at<double>(s->L.fwc);
+    double* w1 = s->at<double>(s->L.fwc1);
+    pr_status r = fno_restrict(s, U, 0.0, w0);
+    if (r != PR_OK) return r;
+    for (int n = 0; n < s->N; ++n) {
+        r = fno_restrict(s, U + (long long)(n + 1) * g.stride, (n + 1) * s->dT, w1);
+        if (r != PR_OK) return r;
+        double* wb = nullptr;
+        if (base == PR_FNO_BASE_LOD) {
+            wb = s->at<double>(s->L.fwb);
+            r = fno_lod_base(s, w0, n, wb);
+            if (r != PR_OK) return r;
+        }
+        HIPCHK(launch_pair(w0, w1, wb, pairs_out + (long long)n * 4 * 64 * 64, s->bcf,
+                           s->grid.s_max, n * s->dT, (n + 1) * s->dT, s->stream));
+        std::swap(w0, w1);
+    }
     HIPCHK(hipStreamSynchronize(s->stream));
     return PR_OK;
 }
@@ -1054,6 +1298,7 @@ pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* m
     int32_t mf = 0, mg = 0;
     pr_status st = parareal_plan(grid, model, opt, &mf, &mg, nullptr, nullptr);
     if (st != PR_OK) return st;
+    if (opt->coarse_kind == PR_G_FNO) return PR_EMODEL;   // requests carry no operator
     Req r;
     r.id = sv->next_id++;
     r.g = *grid;

@@ -39,7 +39,8 @@ class Fno:
     the activations of up to ``max_batch`` samples)."""
 
     def __init__(self, max_batch: int = 1, precision: int = L.PR_FNO_FP32,
-                 out_scale: float = 1.0, device=None, stream=None):
+                 out_scale: float = 1.0, base: int = L.PR_FNO_BASE_IDENTITY, device=None,
+                 stream=None):
         import torch
         self.device = torch.device(device or "cuda")
         self.stream = stream or torch.cuda.current_stream(self.device)
@@ -48,13 +49,14 @@ class Fno:
         if nbytes == 0:
             raise L.PararealError(L.PR_EINVAL, f"max_batch {max_batch} out of range")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        cfg = L.pr_fno_config(max_batch, precision, out_scale)
+        cfg = L.pr_fno_config(max_batch, precision, out_scale, base, 0)
         h = C.c_void_p()
         _check(lib.pr_fno_create(C.byref(cfg), C.c_void_p(self.ws.data_ptr()), nbytes,
                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)), "pr_fno_create")
         self.handle = h
         self.max_batch = max_batch
         self.out_scale = out_scale
+        self.base = base
         self.n_params = param_count()
 
     # -- parameters ---------------------------------------------------------

@@ -27,7 +27,8 @@ def _stats_dict(st: L.pr_stats) -> dict:
                 t_total_ms=st.t_total_ms, t_fine_ms=st.t_fine_ms, t_chain_ms=st.t_chain_ms,
                 t_correct_ms=st.t_correct_ms, fine_point_steps=st.fine_point_steps,
                 fine_step_launches=st.fine_step_launches, fine_step_bytes=st.fine_step_bytes,
-                t_step_kernels_ms=st.t_step_kernels_ms, workspace_bytes=st.workspace_bytes)
+                t_step_kernels_ms=st.t_step_kernels_ms, workspace_bytes=st.workspace_bytes,
+                coarse_fallback=st.coarse_fallback)
 
 
 def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
@@ -110,6 +111,38 @@ class Solver:
         status = L.lib().parareal_apply(self._h, op, slice_, C.c_void_p(x.data_ptr()),
                                         C.c_void_p(out.data_ptr()))
         L.check(status, "parareal_apply", self._h)
+        return out
+
+    def attach_fno(self, fno) -> None:
+        """PR_G_FNO: use the operator of a paper_2404_02521_amd.fno.Fno handle as G."""
+        L.check(L.lib().parareal_attach_fno(self._h, fno.handle), "parareal_attach_fno", self._h)
+        self._fno = fno
+
+    def fno_pair(self, slice_: int, v0, v1, base: int = L.PR_FNO_BASE_IDENTITY, out=None):
+        """PR_G_FNO: training pair [w_in, B1, V_in, V_tgt] (4, 64, 64) float32 of slice
+        `slice_` from the full fine grids v0 (at its start) and v1 (at its end)."""
+        import torch
+        for x in (v0, v1):
+            assert x.dtype == torch.float64 and x.is_contiguous() and x.shape == (self.inst.M,) * 2
+        if out is None:
+            out = torch.empty((4, 64, 64), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == 4 * 64 * 64
+        L.check(L.lib().parareal_fno_pair(self._h, slice_, C.c_void_p(v0.data_ptr()),
+                                          C.c_void_p(v1.data_ptr()), base,
+                                          C.c_void_p(out.data_ptr())),
+                "parareal_fno_pair", self._h)
+        return out
+
+    def fno_pairs(self, base: int = L.PR_FNO_BASE_IDENTITY, out=None):
+        """PR_G_FNO: the N training pairs (N, 4, 64, 64) float32 of the serial-F
+        trajectory from the payoff."""
+        import torch
+        N = self.inst.n_slices
+        if out is None:
+            out = torch.empty((N, 4, 64, 64), dtype=torch.float32, device=self.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == N * 4 * 64 * 64
+        L.check(L.lib().parareal_fno_pairs(self._h, base, C.c_void_p(out.data_ptr())),
+                "parareal_fno_pairs", self._h)
         return out
 
     def close(self):
