@@ -64,6 +64,9 @@ def main():
                     help="skip the error check against serial F (counter runs only)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--no-fno", action="store_true", help="skip the neural coarse propagator leg")
+    ap.add_argument("--fno-train-s", type=float, default=30.0,
+                    help="training budget of the neural coarse propagator leg (seconds)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
@@ -167,6 +170,8 @@ def main():
     if not args.no_check:
         out["lod_coarse"] = lod_leg(pr, insts, seeds, serial_ref)
         out["serving"] = serving_leg(pr)
+        if not args.no_fno:
+            out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
     if args.max_iters:
         out["note"] = "iterations capped at %d (counter run, not a bench line)" % args.max_iters
     if not args.no_cpu_baseline and not args.no_check:
@@ -196,6 +201,78 @@ def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
             "p50_ms": round(nearest_rank(lat, 50), 3), "p99_ms": round(nearest_rank(lat, 99), 3),
             "iters": iters, "max_err_vs_serial_f": max(errs),
             "parareal_ms": [round(x, 2) for x in lat]}
+
+
+def fno_flops_per_sample():
+    """Algorithmic FLOPs of one forward pass of the operator (multiply-adds x 2):
+    lift, four Fourier layers (pointwise W, truncated DFTs as real products,
+    per-mode mixing, inverse DFTs) and projection."""
+    P = 64 * 64
+    lift = 2 * P * (7 * 64 + 64 * 32)
+    layer = (2 * P * 32 * 32 + 2 * 64 * 24 * 64 * 32 + 2 * 24 * 24 * 128 * 32
+             + 2 * 576 * 64 * 32 + 2 * 12 * 128 * 48 * 32 + 2 * 64 * 64 * 24 * 32)
+    proj = 2 * P * (32 * 128 + 128)
+    return lift + 4 * layer + proj
+
+
+def fno_leg(pr, insts, seeds, serial_ref, train_s):
+    """Neural coarse propagator: pairs from serial F on 48 seed-drawn 257^2
+    trajectories (N = 64, T = 1), BF16 training for a fixed budget, then Parareal
+    with the trained operator as G on the bench instances (LOD fallback on)."""
+    import torch
+    from paper_2404_02521_amd import _lib as L
+    from paper_2404_02521_amd.fno import Fno
+    from paper_2404_02521_amd.train import evaluate, generate_pairs, init_params, train
+    from synthetic import plain_at_scale
+    dT = 1.0 / 64
+    t = time.perf_counter()
+    pairs, meta = generate_pairs([plain_at_scale(1000 + i, M=257) for i in range(48)])
+    vp, vm = generate_pairs([plain_at_scale(2000 + i, M=257) for i in range(4)])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t
+    flat = init_params(0).cuda()
+    net = Fno(max_batch=64, out_scale=dT)
+    net.set_params(flat)
+    zero = Fno(max_batch=64, out_scale=dT)
+    zero.set_params(torch.zeros_like(flat))
+    v_zero = evaluate(zero, vp, vm, dT)
+    v_init = evaluate(net, vp, vm, dT)
+    zero.close()
+    hist = train(net, pairs, meta, dT, 10 ** 6, 64, L.PR_FNO_BF16, log_every=1000,
+                 time_budget_s=train_s)
+    steps, t_train = hist[-1][1], hist[-1][-1]
+    v_tr = evaluate(net, vp, vm, dT)
+    flops = 3.0 * fno_flops_per_sample() * 64 * steps
+    params = net.params()
+    net.close()
+    res = {"K": [], "ms": [], "err": [], "fallback": []}
+    for s_, inst in zip(seeds, insts):
+        fi = Fno(max_batch=1, out_scale=dT)
+        fi.set_params(params)
+        sv = pr.Solver(inst, coarse_kind=pr.PR_G_FNO)
+        sv.attach_fno(fi)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = sv.solve()
+        res["ms"].append(round((time.perf_counter() - a) * 1e3, 1))
+        res["K"].append(r.iters)
+        res["fallback"].append(r.stats["coarse_fallback"])
+        ref = serial_ref[s_]
+        res["err"].append(float((r.value - ref).abs().max() / ref.abs().max()))
+        sv.close()
+        fi.close()
+    return {"workload": "FNO width 32, 4 layers, 12x12 modes, 64^2, BF16 MFMA training on %d pairs "
+                        "(48 seed-drawn 257^2 F trajectories, N=64) for %.0f s; then G on the "
+                        "513^2 bench instances through DST transfers" % (pairs.shape[0], train_s),
+            "data_s": round(t_data, 2), "train_steps": steps, "train_s": round(t_train, 2),
+            "train_samples_per_s": round(64 * steps / t_train, 1),
+            "train_tflops": round(flops / t_train / 1e12, 3),
+            "train_mfma_frac_bf16": round(flops / t_train / 2.5e15, 5),
+            "val_data_mse": {"untrained": v_init[1], "without_network": v_zero[1],
+                             "trained": v_tr[1]},
+            "parareal": {"iters": res["K"], "ms": res["ms"], "max_err_vs_serial_f": max(res["err"]),
+                         "coarse_fallback": res["fallback"],
+                         "solves_per_s": round(len(res["ms"]) / (sum(res["ms"]) * 1e-3), 4)}}
 
 
 def serving_leg(pr, rate=30.0, count=120, seed=11, sides=(129, 257)):

@@ -15,6 +15,35 @@ import time
 from . import _lib as L
 
 
+# parameter blocks of the flat vector (include/parareal.h): name, shape, fan-in
+def _blocks():
+    b = [("L1", (7, 64), 7), ("l1", (64,), 7), ("L2", (64, 32), 64), ("l2", (32,), 64)]
+    for l in range(4):
+        b += [(f"Rr{l}", (24, 12, 32, 32), 0), (f"Ri{l}", (24, 12, 32, 32), 0),
+              (f"W{l}", (32, 32), 32), (f"b{l}", (32,), 32)]
+    b += [("P1", (32, 128), 32), ("p1", (128,), 32), ("P2", (128, 1), 128), ("p2", (1,), 128)]
+    return b
+
+
+def init_params(seed: int = 0):
+    """Initial flat FP32 parameter vector: dense weights and biases uniform in
+    +-1/sqrt(fan_in), spectral multipliers uniform in [0, 1/32^2) (real and
+    imaginary parts), drawn block by block in vector order."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape, fan in _blocks():
+        if fan == 0:
+            parts.append(rng.uniform(0.0, 1.0, size=shape).ravel() / (32 * 32))
+        else:
+            bound = 1.0 / np.sqrt(fan)
+            parts.append(rng.uniform(-bound, bound, size=shape).ravel())
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == int(L.lib().pr_fno_param_count())
+    return torch.from_numpy(flat)
+
+
 def lr_at(epoch: int, lr0: float = 1e-3, decay: float = 0.96, every: int = 25) -> float:
     return lr0 * decay ** (epoch // every)
 
