@@ -34,6 +34,28 @@ HBM_PEAK_GBS = 8000.0
 SEEDS = list(range(8))
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2404_02521_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic_per_point_step():
+    """HBM bytes per interior point-step of the step kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated),
+    or None when no summary matches the current kernel source."""
+    import glob
+    want = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        txt = open(f).read()
+        if "kernel_source_sha256: " + want not in txt:
+            continue
+        for line in txt.splitlines():
+            if line.startswith("traffic_bytes_per_point_step:"):
+                return float(line.split(":", 1)[1])
+    return None
+
+
 def nearest_rank(xs, p):
     xs = sorted(xs)
     k = max(1, math.ceil(p / 100.0 * len(xs)))
@@ -135,6 +157,10 @@ def main():
 
     value = args.steps / total
     achieved = steps_bytes / (steps_ms * 1e-3) / 1e9 if steps_ms > 0 else 0.0
+    tpp = measured_traffic_per_point_step()
+    # algorithmic bytes are 12 B per point-step, so the average launch's point-steps
+    # are bytes_per_launch / 12
+    traffic = None if tpp is None else round(tpp * steps_bytes / 12.0 / max(1, steps_launch))
     avg_launch_us = steps_ms * 1e3 / max(1, steps_launch)
     out = {
         "metric": METRIC,
@@ -162,8 +188,10 @@ def main():
         "phase_ms": {"fine_sweeps": round(fine_ms, 2), "coarse_chain": round(chain_ms, 2),
                      "correction": round(corr_ms, 2), "step_kernels": round(steps_ms, 2)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_fine_tb<MODE_INCR, S=4> (FP32 increment form, 4 explicit steps per launch, 12 B per point-step)",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel_source_sha256": kernel_source_hash(),
+                     "kernel": "k_fine_tb<MODE_INCR, S=6> (FP32 increment form, 6 explicit steps per launch "
+                               "in registers, 12 B per point-step algorithmic)",
                      "avg_launch_us": round(avg_launch_us, 3),
                      "bytes_per_launch": round(steps_bytes / max(1, steps_launch))},
     }

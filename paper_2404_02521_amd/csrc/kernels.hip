@@ -24,6 +24,15 @@ namespace pr {
 
 enum { MODE_DIRECT = 0, MODE_INCR = 1, MODE_PREP = 2 };
 
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled.
+template <int N, int I = 0, class Fn>
+__device__ __attribute__((always_inline)) inline void static_for(Fn&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Fine stencil step.  Each wavefront owns a strip of 64 consecutive interior
 // columns and a chunk of `rows` consecutive rows of one slice.  It walks down
@@ -149,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
 // MODE_INCR: FP32 increments d over an FP64 base (d+ = d + dt (Lb + L d));
 // MODE_DIRECT: FP64 state (u+ = u + dt L u).
 // ---------------------------------------------------------------------------
-template <int MODE, bool CHEAP, typename T, int S>
+template <int MODE, bool CHEAP, typename T, int S, int PF>
 __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                                                     const float* __restrict__ lb,
                                                     T* __restrict__ out, StepArgs a) {
@@ -201,21 +210,24 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     const T rr = (T)a.c.r;
     const T dt = (T)a.dt;
 
-    // Window of level q (0..S-1): three rows as (l, c, r) in slots 0..2; with
-    // the row loop unrolled by 3 the newest row of iteration x sits in slot
-    // x % 3, so rotating the window costs no moves.
-    T wl[S][3], wc[S][3], wr[S][3];
+    // Window of level q (0..S-1): three rows in slots 0..2; with the row loop
+    // unrolled by 3 the newest row of iteration x sits in slot x % 3, so
+    // rotating the window costs no moves.  Only the lane's own column is
+    // kept: the j +- 1 neighbours come from DPP shifts when a level is
+    // evaluated (the mixed term needs only the shifts of u_{i+1} - u_{i-1}).
+    T wc[S][3];
     float lbw[S];   // Lb rows x-1 .. x-S (lbw[q-1] -> row x-q)
 #pragma unroll
     for (int q = 0; q < S; ++q) {
         lbw[q] = 0.f;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) { wl[q][k] = T(0); wc[q][k] = T(0); wr[q][k] = T(0); }
+        for (int k = 0; k < 3; ++k) wc[q][k] = T(0);
     }
 
     const int x0 = max(0, ia - S);
     const int x1 = ib - 1 + S;   // last iteration (level S row ib-1)
-    // Prefetch queue: raw loads of rows x..x+2 and Lb rows x-1..x+1 in flight.
+    // Prefetch queue: raw loads of rows x..x+PF-1 and Lb rows x-1..x+PF-2 in
+    // flight (PF a multiple of 3; row x in slot x % PF).
     auto raw = [&](int x) -> T {
         return (x >= 1 && x <= M - 2 && in_col) ? src[(long long)(x - 1) * P + (jl - 1)] : T(0);
     };
@@ -224,28 +236,30 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                    ? lbs[(long long)(rl - 1) * P + (jl - 1)]
                    : 0.f;
     };
-    T pq[3];
-    float lq[3];
-    // slot of row x is x % 3
+    static_assert(PF % 3 == 0, "prefetch depth must be a multiple of the window");
+    T pq[PF];
+    float lq[PF];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int xr = x0 + ((k - x0 % 3) + 3) % 3;   // the row in [x0, x0+2] with xr % 3 == k
+    for (int k = 0; k < PF; ++k) {
+        const int xr = x0 + ((k - x0 % PF) + PF) % PF;   // the row in [x0, x0+PF) with xr % PF == k
         pq[k] = raw(xr);
         lq[k] = rawlb(xr - 1);
     }
 
-    // One row iteration; the newest window slot is x % 3 = K (compile time).
+    // One row iteration; the newest window slot is x % 3 = K and the prefetch
+    // slot x % PF = KP (both compile time).
     // FAST (compile time): every row touched (x-S .. x) is interior and no lane
     // is on the ring, so no boundary logic is compiled in.
-    auto iter = [&](auto Kc, auto Fc, int x) __attribute__((always_inline)) {
-        constexpr int K = decltype(Kc)::value;
+    auto iter = [&](auto KPc, auto Fc, int x) __attribute__((always_inline)) {
+        constexpr int KP = decltype(KPc)::value;
+        constexpr int K = KP % 3;
         constexpr bool FAST = decltype(Fc)::value;
         constexpr int K1 = (K + 2) % 3;   // previous row
         constexpr int K2 = (K + 1) % 3;   // row before that
-        const T cur_raw = pq[K];
-        const float cur_lb = lq[K];
-        pq[K] = raw(x + 3);
-        lq[K] = rawlb(x + 2);
+        const T cur_raw = pq[KP];
+        const float cur_lb = lq[KP];
+        pq[KP] = raw(x + PF);
+        lq[KP] = rawlb(x + PF - 1);
         if (MODE == MODE_INCR) {
 #pragma unroll
             for (int q = S - 1; q > 0; --q) lbw[q] = lbw[q - 1];
@@ -262,18 +276,19 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                         c = cur_raw;
                 }
             }
-            wl[0][K] = shr1(c); wc[0][K] = c; wr[0][K] = shl1(c);
+            wc[0][K] = c;
         }
 #pragma unroll
         for (int q = 1; q <= S; ++q) {
             const int row = x - q;
             const T um = wc[q - 1][K2], u0 = wc[q - 1][K1], up = wc[q - 1][K];
-            const T lm = wl[q - 1][K2], l0 = wl[q - 1][K1], lp = wl[q - 1][K];
-            const T rm = wr[q - 1][K2], r0 = wr[q - 1][K1], rp = wr[q - 1][K];
+            const T l0 = shr1(u0), r0 = shl1(u0);
+            const T dd = up - um;
+            const T mix = shl1(dd) - shr1(dd);   // (r+ - l+) - (r- - l-)
             const T fi = (T)row;
             const T A = a1 * fi * fi, Mu = hr * fi, G = gj * fi;
-            const T L = A * (up - T(2) * u0 + um) + bj * (r0 - T(2) * u0 + l0) +
-                        G * (rp + lm - lp - rm) + Mu * (up - um) + nj * (r0 - l0) - rr * u0;
+            const T L = A * (up - T(2) * u0 + um) + bj * (r0 - T(2) * u0 + l0) + G * mix +
+                        Mu * dd + nj * (r0 - l0) - rr * u0;
             T c = (MODE == MODE_INCR) ? u0 + dt * ((T)lbw[q - 1] + L) : u0 + dt * L;
             if (!FAST) {
                 if (row < 0 || row > M - 1)
@@ -284,32 +299,24 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
             if (q == S) {
                 if (row >= ia && row < ib && out_lane) dst[(long long)(row - 1) * P + (jl - 1)] = c;
             } else {
-                wl[q][K] = shr1(c); wc[q][K] = c; wr[q][K] = shl1(c);
+                wc[q][K] = c;
             }
         }
     };
     using F0 = std::integral_constant<bool, false>;
     using F1 = std::integral_constant<bool, true>;
-    using C0 = std::integral_constant<int, 0>;
-    using C1 = std::integral_constant<int, 1>;
-    using C2 = std::integral_constant<int, 2>;
     auto general = [&](int x) __attribute__((always_inline)) {
-        switch (x % 3) {
-            case 0: iter(C0{}, F0{}, x); break;
-            case 1: iter(C1{}, F0{}, x); break;
-            default: iter(C2{}, F0{}, x); break;
-        }
+        static_for<PF>([&](auto Kc) {
+            if (x % PF == decltype(Kc)::value) iter(Kc, F0{}, x);
+        });
     };
     // interior iterations: x in [S+1, M-2] for strips away from the ring columns
     const int fb = strip_inner ? max(x0, S + 1) : x1 + 1;
     const int fe = strip_inner ? min(x1, M - 2) : x1;
     int x = x0;
-    while (x <= x1 && (x < fb || x % 3 != 0)) general(x++);
-    for (; x + 2 <= fe; x += 3) {
-        iter(C0{}, F1{}, x);
-        iter(C1{}, F1{}, x + 1);
-        iter(C2{}, F1{}, x + 2);
-    }
+    while (x <= x1 && (x < fb || x % PF != 0)) general(x++);
+    for (; x + PF - 1 <= fe; x += PF)
+        static_for<PF>([&](auto Kc) { iter(Kc, F1{}, x + decltype(Kc)::value); });
     while (x <= x1) general(x++);
 }
 
@@ -620,15 +627,19 @@ static hipError_t launch_step(const TI* in, const float* lb, TO* out, float* out
     return hipGetLastError();
 }
 
+// Rows in flight per wavefront: 3 measured faster than 6 on the 513^2 x 64
+// slice workload (deeper queues cost occupancy).
+constexpr int kTbPrefetch = 3;
+
 template <int MODE, typename T, int S>
 static void launch_tb_s(const T* in, const float* lb, T* out, const StepArgs& a, hipStream_t st) {
     const int blocks = (step_waves(a) + 3) / 4;
     if (a.bc.kind == 2)
-        hipLaunchKernelGGL((k_fine_tb<MODE, false, T, S>), dim3(blocks), dim3(kBlock), 0, st, in,
-                           lb, out, a);
+        hipLaunchKernelGGL((k_fine_tb<MODE, false, T, S, kTbPrefetch>), dim3(blocks), dim3(kBlock),
+                           0, st, in, lb, out, a);
     else
-        hipLaunchKernelGGL((k_fine_tb<MODE, true, T, S>), dim3(blocks), dim3(kBlock), 0, st, in,
-                           lb, out, a);
+        hipLaunchKernelGGL((k_fine_tb<MODE, true, T, S, kTbPrefetch>), dim3(blocks), dim3(kBlock),
+                           0, st, in, lb, out, a);
 }
 
 template <int MODE, typename T>

@@ -214,7 +214,8 @@ struct pr_solver {
     std::vector<hipEvent_t> step_ev;   // PR_FLAG_TIME_STEPS: a pair per step launch
     int step_ev_used = 0;
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
-    int fuse = 4;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
+    int fuse = 6;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
+    int wave_target = 6144;            // wavefronts a step launch aims for (PR_STEP_WAVES)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
     std::map<int, double> graph_bytes;
     int64_t sweep_launches = 0;        // step launches of the last fine_sweep
@@ -269,7 +270,7 @@ StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, i
     StepArgs a = step_args(s, g, s->bcf, dt, first, count, step);
     const int W = kWave - 2 * S;
     a.nstrips = (g.nin + W - 1) / W;
-    long long target = 5120;
+    const long long target = s->wave_target;
     long long rows = (long long)g.nin * a.nstrips * count / target;
     rows = std::max<long long>(8, std::min<long long>(128, rows));
     if (s->rows_override > 0) rows = s->rows_override;
@@ -870,6 +871,7 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     s->ring_max_T = host_ring_max(s, model->T);
     if (const char* e = std::getenv("PR_STEP_ROWS")) s->rows_override = std::atoi(e);
     if (const char* e = std::getenv("PR_STEP_FUSE")) s->fuse = std::max(1, std::min(8, std::atoi(e)));
+    if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
     if (!s->fineg) {
         hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));
         if (e != hipSuccess) {

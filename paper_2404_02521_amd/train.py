@@ -109,4 +109,7 @@ def train(net, pairs, meta, dT: float, epochs: int, batch: int = 64,
         if time_budget_s and time.perf_counter() - t0 > time_budget_s:
             break
     torch.cuda.synchronize()
+    if not hist or hist[-1][1] != step:   # stopped between logged epochs
+        nan = float("nan")
+        hist.append((ep, step, nan, nan, nan, time.perf_counter() - t0))
     return hist
