@@ -40,19 +40,20 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic_per_point_step():
-    """HBM bytes per interior point-step of the step kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated),
-    or None when no summary matches the current kernel source."""
-    import glob
-    want = kernel_source_hash()
-    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
-        txt = open(f).read()
-        if "kernel_source_sha256: " + want not in txt:
-            continue
-        for line in txt.splitlines():
-            if line.startswith("traffic_bytes_per_point_step:"):
-                return float(line.split(":", 1)[1])
+def measured_traffic_per_point_step(name="k_fine_tb_513x513x64_fp32.md"):
+    """HBM bytes per interior point-step of the step kernel on the headline
+    workload, from its committed rocprofv3 counter summary (FETCH_SIZE x2 +
+    WRITE_SIZE x1, copy-calibrated), or None when that summary was taken on
+    another version of the kernel source."""
+    f = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(f):
+        return None
+    txt = open(f).read()
+    if "kernel_source_sha256: " + kernel_source_hash() not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("traffic_bytes_per_point_step:"):
+            return float(line.split(":", 1)[1])
     return None
 
 
@@ -87,6 +88,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--no-fno", action="store_true", help="skip the neural coarse propagator leg")
+    ap.add_argument("--largest-share-only", action="store_true",
+                    help="run only the 2049^2 x 32-slice step-kernel leg and print its JSON")
     ap.add_argument("--fno-train-s", type=float, default=30.0,
                     help="training budget of the neural coarse propagator leg (seconds)")
     args = ap.parse_args()
@@ -104,6 +107,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.largest_share_only:
+        if args.copy_probe_mib:
+            n = args.copy_probe_mib << 20
+            src = torch.ones(n, dtype=torch.uint8, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps(largest_share_leg(pr)), flush=True)
+        return
     seeds = SEEDS[: args.seeds]
     insts = [plain_at_scale(s) for s in seeds]
     if args.copy_probe_mib:
@@ -198,6 +212,7 @@ def main():
     if not args.no_check:
         out["lod_coarse"] = lod_leg(pr, insts, seeds, serial_ref)
         out["serving"] = serving_leg(pr)
+        out["largest_share"] = largest_share_leg(pr)
         if not args.no_fno:
             out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
     if args.max_iters:
@@ -229,6 +244,31 @@ def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
             "p50_ms": round(nearest_rank(lat, 50), 3), "p99_ms": round(nearest_rank(lat, 99), 3),
             "iters": iters, "max_err_vs_serial_f": max(errs),
             "parareal_ms": [round(x, 2) for x in lat]}
+
+
+def largest_share_leg(pr):
+    """The step kernel at the shape one GPU would hold of the largest problem:
+    2049^2 grid, 32 of its 256 slices (slice length 2/256, 7207 explicit steps per
+    slice at 0.9 of the bound), one Parareal iteration (the fine sweep over all 32
+    slices; the same-grid implicit G).  Achieved = 12 B per interior point-step
+    over the HIP-event time of the step launches."""
+    import torch
+    from synthetic import largest_single
+    inst = largest_single().replace(n_slices=32, T=2.0 / 8, coarse_steps_per_slice=4)
+    sv = pr.Solver(inst, coarse_kind=pr.PR_G_LOD, flags=pr.PR_FLAG_TIME_STEPS, max_iters=1)
+    sv.solve()
+    torch.cuda.synchronize()
+    r = sv.solve()
+    st = r.stats
+    sv.close()
+    ach = st["fine_step_bytes"] / (st["t_step_kernels_ms"] * 1e-3) / 1e9
+    return {"workload": "2049^2 FP32 increment form, 32 slices of dT = 2/256 (one of 8 GPUs' "
+                        "share of the 256-slice problem), %d explicit steps per slice, one "
+                        "fine sweep" % st["fine_steps"],
+            "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+            "step_launches": st["fine_step_launches"],
+            "avg_launch_us": round(st["t_step_kernels_ms"] * 1e3 / max(1, st["fine_step_launches"]), 2),
+            "point_steps_per_s": round(st["fine_point_steps"] / (st["t_step_kernels_ms"] * 1e-3), 1)}
 
 
 def fno_flops_per_sample():
