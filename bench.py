@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--no-fno", action="store_true", help="skip the neural coarse propagator leg")
+    ap.add_argument("--fno-train-only", action="store_true",
+                    help="run only the training part of the neural coarse propagator leg")
     ap.add_argument("--largest-share-only", action="store_true",
                     help="run only the 2049^2 x 32-slice step-kernel leg and print its JSON")
     ap.add_argument("--fno-train-s", type=float, default=30.0,
@@ -117,6 +119,9 @@ def main():
             torch.cuda.synchronize()
             del src, dst
         print(json.dumps(largest_share_leg(pr)), flush=True)
+        return
+    if args.fno_train_only:
+        print(json.dumps(fno_leg(pr, [], [], {}, args.fno_train_s, parareal=False)), flush=True)
         return
     seeds = SEEDS[: args.seeds]
     insts = [plain_at_scale(s) for s in seeds]
@@ -283,7 +288,7 @@ def fno_flops_per_sample():
     return lift + 4 * layer + proj
 
 
-def fno_leg(pr, insts, seeds, serial_ref, train_s):
+def fno_leg(pr, insts, seeds, serial_ref, train_s, parareal=True):
     """Neural coarse propagator: pairs from serial F on 48 seed-drawn 257^2
     trajectories (N = 64, T = 1), BF16 training for a fixed budget, then Parareal
     with the trained operator as G on the bench instances (LOD fallback on)."""
@@ -314,7 +319,7 @@ def fno_leg(pr, insts, seeds, serial_ref, train_s):
     params = net.params()
     net.close()
     res = {"K": [], "ms": [], "err": [], "fallback": []}
-    for s_, inst in zip(seeds, insts):
+    for s_, inst in zip(seeds, insts) if parareal else []:
         fi = Fno(max_batch=1, out_scale=dT)
         fi.set_params(params)
         sv = pr.Solver(inst, coarse_kind=pr.PR_G_FNO)
@@ -338,9 +343,10 @@ def fno_leg(pr, insts, seeds, serial_ref, train_s):
             "train_mfma_frac_bf16": round(flops / t_train / 2.5e15, 5),
             "val_data_mse": {"untrained": v_init[1], "without_network": v_zero[1],
                              "trained": v_tr[1]},
-            "parareal": {"iters": res["K"], "ms": res["ms"], "max_err_vs_serial_f": max(res["err"]),
-                         "coarse_fallback": res["fallback"],
-                         "solves_per_s": round(len(res["ms"]) / (sum(res["ms"]) * 1e-3), 4)}}
+            "parareal": None if not parareal else {
+                "iters": res["K"], "ms": res["ms"], "max_err_vs_serial_f": max(res["err"]),
+                "coarse_fallback": res["fallback"],
+                "solves_per_s": round(len(res["ms"]) / (sum(res["ms"]) * 1e-3), 4)}}
 
 
 def serving_leg(pr, rate=30.0, count=120, seed=11, sides=(129, 257)):

@@ -95,9 +95,11 @@ __device__ inline short to_bf16(float f) {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// MF = true: BF16 MFMA (T = float only).  Block tile BM x BN, 256 threads.
+// MF = true: BF16 MFMA (T = float only).  Block tile BM x BN (32x32, 64x32,
+// 128x32 or 64x64), 256 threads.
 //   FMA : thread (tx, ty) of a 16 x 16 grid owns rows ty + 16 i, columns tx + 16 j.
-//   MFMA: four wavefronts, each a 32 x 32 sub-tile of 2 x 2 16x16x16 blocks.
+//   MFMA: four wavefronts in a WM x WN grid, each a (16 PM) x (16 QN) sub-tile of
+//         16x16x16 blocks.
 template <typename T, int BM, int BN, bool MF>
 __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
     __shared__ T As[KT][BM + 1];
@@ -115,18 +117,21 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
     const bool b_nfast = g.b.cs == 1;
 
     constexpr int TM = BM / 16, TN = BN / 16;
-    constexpr int WN = BN / 32;   // MFMA wave grid (BM/32) x (BN/32) = 4 waves
+    constexpr int WN = (BN >= 64 || BM < 128) ? 2 : 1;   // MFMA wave grid WM x WN = 4 waves
+    constexpr int WM = 4 / WN;
+    constexpr int PM = BM / (16 * WM), QN = BN / (16 * WN);
+    static_assert(PM >= 1 && QN >= 1 && PM * 16 * WM == BM && QN * 16 * WN == BN, "tile");
     const int tx = tid & 15, ty = tid >> 4;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave / WN, wn = wave % WN;
 
     T acc[TM][TN];
-    f32x4 macc[2][2];
+    f32x4 macc[PM][QN];
     if constexpr (MF) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < PM; ++p)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) macc[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < QN; ++q) macc[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     } else {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -152,21 +157,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
 #pragma unroll
             for (int ks = 0; ks < KT; ks += 16) {
                 const int kb = ks + (lane >> 4) * 4;
-                bf16x4 af[2], bfr[2];
+                bf16x4 af[PM], bfr[QN];
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    const int row = wm * 32 + p * 16 + (lane & 15);
-                    const int col = wn * 32 + p * 16 + (lane & 15);
+                for (int p = 0; p < PM; ++p) {
+                    const int row = wm * 16 * PM + p * 16 + (lane & 15);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        af[p][e] = to_bf16((float)As[kb + e][row]);
-                        bfr[p][e] = to_bf16((float)Bs[kb + e][col]);
-                    }
+                    for (int e = 0; e < 4; ++e) af[p][e] = to_bf16((float)As[kb + e][row]);
                 }
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+                for (int q = 0; q < QN; ++q) {
+                    const int col = wn * 16 * QN + q * 16 + (lane & 15);
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
+                    for (int e = 0; e < 4; ++e) bfr[q][e] = to_bf16((float)Bs[kb + e][col]);
+                }
+#pragma unroll
+                for (int p = 0; p < PM; ++p)
+#pragma unroll
+                    for (int q = 0; q < QN; ++q)
                         macc[p][q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[p], bfr[q],
                                                                               macc[p][q], 0, 0, 0);
             }
@@ -199,13 +206,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
     };
     if constexpr (MF) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < PM; ++p)
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < QN; ++q)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    store(m0 + wm * 32 + p * 16 + (lane >> 4) * 4 + e,
-                          n0 + wn * 32 + q * 16 + (lane & 15), (T)macc[p][q][e]);
+                    store(m0 + wm * 16 * PM + p * 16 + (lane >> 4) * 4 + e,
+                          n0 + wn * 16 * QN + q * 16 + (lane & 15), (T)macc[p][q][e]);
     } else {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -255,17 +262,28 @@ template <typename T>
 static hipError_t run(const Gemm<T>& q, bool mfma, hipStream_t st) {
     if (q.g.M <= 0 || q.g.N <= 0 || q.g.K <= 0) return hipErrorInvalidValue;
     if ((long long)q.n0 * q.g.n1 * q.g.n2 > 65535) return hipErrorInvalidValue;
-    const bool narrow = q.g.N <= 32 && q.g.M >= 128;
+    // tile by output shape: small outputs (the truncated transforms) would
+    // leave most of a 64 x 64 tile idle
+    const int M = q.g.M, N = q.g.N;
+    const int shape = (N <= 32) ? (M <= 32 ? 0 : (M <= 64 ? 1 : 2)) : 3;
     if constexpr (std::is_same<T, float>::value) {
         if (mfma) {
-            if (narrow) launch_tile<float, 128, 32, true>(q, st);
-            else launch_tile<float, 64, 64, true>(q, st);
+            switch (shape) {
+                case 0: launch_tile<float, 32, 32, true>(q, st); break;
+                case 1: launch_tile<float, 64, 32, true>(q, st); break;
+                case 2: launch_tile<float, 128, 32, true>(q, st); break;
+                default: launch_tile<float, 64, 64, true>(q, st); break;
+            }
         } else {
-            if (narrow) launch_tile<float, 128, 32, false>(q, st);
-            else launch_tile<float, 64, 64, false>(q, st);
+            switch (shape) {
+                case 0: launch_tile<float, 32, 32, false>(q, st); break;
+                case 1: launch_tile<float, 64, 32, false>(q, st); break;
+                case 2: launch_tile<float, 128, 32, false>(q, st); break;
+                default: launch_tile<float, 64, 64, false>(q, st); break;
+            }
         }
     } else {
-        (void)mfma; (void)narrow;
+        (void)mfma; (void)shape;
         launch_tile<T, 64, 64, false>(q, st);
     }
     return hipGetLastError();
