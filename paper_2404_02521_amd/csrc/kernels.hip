@@ -347,13 +347,20 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
     const long long FS = a.fg.stride;
     const int FP = a.fg.pitch;
     const double hc = a.bc.h;
-    T* tab = reinterpret_cast<T*>(lds);                 // 3*nc row coefficients
-    T* buf0 = tab + ((3 * nc + 1) / 2) * 2;            // nc*nc
+    // Row weights of the operator in the form
+    //   L = (A+Mu) u_{I+1} + (A-Mu) u_{I-1} + (B+Nu) u_{J+1} + (B-Nu) u_{J-1}
+    //       + G (mixed difference) - (2A + 2B + r) u,
+    // A = a1 I^2, Mu = hr I, B = a2 J^2, Nu = hr J, G = g12 I J: per row
+    // [A+Mu, A-Mu, 2A+r, g12 I] in LDS (read as a broadcast), per column in registers.
+    T* tab = reinterpret_cast<T*>(lds);                 // 4*nc row weights
+    T* buf0 = tab + 4 * nc;                            // nc*nc
     T* buf1 = buf0 + nn;                               // nc*nc
     for (int I = tid; I < nc; I += kChainThreads) {
-        tab[3 * I] = (T)(a.c.a1 * I * I);
-        tab[3 * I + 1] = (T)(a.c.hr * I);
-        tab[3 * I + 2] = (T)(a.c.g12 * I);
+        const double A = a.c.a1 * I * I, Mu = a.c.hr * I;
+        tab[4 * I] = (T)(A + Mu);
+        tab[4 * I + 1] = (T)(A - Mu);
+        tab[4 * I + 2] = (T)(2.0 * A + a.c.r);
+        tab[4 * I + 3] = (T)(a.c.g12 * I);
     }
     // Ring nodes: thread tid < 4*(nc-1) owns ring node number tid.
     const bool ring_thread = tid < 4 * (nc - 1);
@@ -375,7 +382,8 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
     const int J = 1 + tid % ncolt;
     const int I0 = 1 + (tid / ncolt) * rows;
     const int nr = (J <= nin) ? max(0, min(rows, nc - 1 - I0)) : 0;
-    const T bJ = (T)(a.c.a2 * J * J), nJ = (T)(a.c.hr * J), fJ = (T)J, rr = (T)a.c.r,
+    const double bJd = a.c.a2 * J * J, nJd = a.c.hr * J;
+    const T cpJ = (T)(bJd + nJd), cmJ = (T)(bJd - nJd), b2J = (T)(2.0 * bJd), fJ = (T)J,
             dt = (T)a.dt;
 
     // c_{k0} = R U_{k0}
@@ -422,10 +430,10 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
                     const int I = I0 + r;
                     const T dnl = cur[(I + 1) * nc + J - 1], dn = cur[(I + 1) * nc + J],
                             dnr = cur[(I + 1) * nc + J + 1];
-                    const T A = tab[3 * I], Mu = tab[3 * I + 1], G = tab[3 * I + 2] * fJ;
-                    const T L = A * (dn - T(2) * c + up) + bJ * (cr - T(2) * c + cl) +
-                                G * (dnr + upl - dnl - upr) + Mu * (dn - up) + nJ * (cr - cl) -
-                                rr * c;
+                    const T* w = tab + 4 * I;
+                    const T wd = w[2] + b2J, G = w[3] * fJ;
+                    const T L = w[0] * dn + w[1] * up + cpJ * cr + cmJ * cl +
+                                G * (dnr + upl - dnl - upr) - wd * c;
                     nxt[I * nc + J] = FP32 ? c + dt * ((T)lbc[I * nc + J] + L) : c + dt * L;
                     upl = cl; up = c; upr = cr;
                     cl = dnl; c = dn; cr = dnr;
@@ -695,7 +703,7 @@ hipError_t chain_set_lds(int bytes) {
 
 int chain_lds_bytes(int nc, int fp32) {
     const int es = fp32 ? 4 : 8;
-    return (((3 * nc + 1) / 2) * 2 + 2 * nc * nc) * es;
+    return (4 * nc + 2 * nc * nc) * es;
 }
 
 hipError_t launch_chain(const double* Ucur, const void* Fold, double* Gold, double* dcor,

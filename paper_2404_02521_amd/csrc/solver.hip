@@ -216,6 +216,7 @@ struct pr_solver {
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
     int fuse = 6;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
     int wave_target = 6144;            // wavefronts a step launch aims for (PR_STEP_WAVES)
+    int min_rows = 8;                  // shortest row chunk of a step launch (PR_STEP_MINROWS)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
     std::map<int, double> graph_bytes;
     int64_t sweep_launches = 0;        // step launches of the last fine_sweep
@@ -272,7 +273,7 @@ StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, i
     a.nstrips = (g.nin + W - 1) / W;
     const long long target = s->wave_target;
     long long rows = (long long)g.nin * a.nstrips * count / target;
-    rows = std::max<long long>(8, std::min<long long>(128, rows));
+    rows = std::max<long long>(s->min_rows, std::min<long long>(128, rows));
     if (s->rows_override > 0) rows = s->rows_override;
     a.rows = (int)std::min<long long>(rows, g.nin);
     a.nchunks = (g.nin + a.rows - 1) / a.rows;
@@ -872,6 +873,7 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     if (const char* e = std::getenv("PR_STEP_ROWS")) s->rows_override = std::atoi(e);
     if (const char* e = std::getenv("PR_STEP_FUSE")) s->fuse = std::max(1, std::min(8, std::atoi(e)));
     if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
+    if (const char* e = std::getenv("PR_STEP_MINROWS")) s->min_rows = std::max(1, std::atoi(e));
     if (!s->fineg) {
         hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));
         if (e != hipSuccess) {
