@@ -218,6 +218,7 @@ def main():
         out["lod_coarse"] = lod_leg(pr, insts, seeds, serial_ref)
         out["serving"] = serving_leg(pr)
         out["largest_share"] = largest_share_leg(pr)
+        out["graph"] = graph_leg(pr)
         if not args.no_fno:
             out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
     if args.max_iters:
@@ -249,6 +250,37 @@ def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
             "p50_ms": round(nearest_rank(lat, 50), 3), "p99_ms": round(nearest_rank(lat, 99), 3),
             "iters": iters, "max_err_vs_serial_f": max(errs),
             "parareal_ms": [round(x, 2) for x in lat]}
+
+
+def graph_leg(pr, reps=5):
+    """hipGraph replay of whole Parareal iterations (PR_FLAG_GRAPH) against eager
+    launches on a launch-bound shape: 129^2, N = 64, same-grid implicit G, seeds
+    0-3; median of `reps` solves each after a warm-up solve (which captures)."""
+    import statistics
+    import torch
+    from synthetic import plain_at_scale
+    res = {}
+    for name, flags in (("eager", 0), ("graph", pr.PR_FLAG_GRAPH)):
+        ms, iters = [], []
+        for seed in range(4):
+            inst = plain_at_scale(seed, M=129, n_slices=64, coarse_M=33)
+            sv = pr.Solver(inst.replace(coarse_steps_per_slice=4), coarse_kind=pr.PR_G_LOD,
+                           flags=flags)
+            sv.solve()
+            torch.cuda.synchronize()
+            t = []
+            for _ in range(reps):
+                a = time.perf_counter()
+                r = sv.solve()
+                t.append((time.perf_counter() - a) * 1e3)
+            ms.append(statistics.median(t))
+            iters.append(r.iters)
+            sv.close()
+        res[name] = {"median_ms": [round(x, 3) for x in ms], "iters": iters}
+    res["speedup"] = round(sum(res["eager"]["median_ms"]) / sum(res["graph"]["median_ms"]), 3)
+    res["workload"] = ("129^2 FP32, N=64, LOD coarse propagator (4 steps per slice), seeds 0-3: "
+                       "eager launches vs one captured graph per iteration")
+    return res
 
 
 def largest_share_leg(pr):
@@ -349,23 +381,36 @@ def fno_leg(pr, insts, seeds, serial_ref, train_s, parareal=True):
                 "solves_per_s": round(len(res["ms"]) / (sum(res["ms"]) * 1e-3), 4)}}
 
 
-def serving_leg(pr, rate=30.0, count=120, seed=11, sides=(129, 257)):
-    """Poisson arrivals of independent solves (seed-drawn parameters, T ~ U[0.25, 2],
-    N in {16, 32, 64}, grid side uniform over `sides`) through the continuous-batching
-    server with the same-grid implicit coarse propagator."""
+def serving_leg(pr, count=120, seed=11, sides=(129, 257)):
+    """Independent solves (seed-drawn parameters, T ~ U[0.25, 2], N in {16, 32, 64},
+    grid side uniform over `sides`) through the continuous-batching server with
+    the same-grid implicit coarse propagator: first all requests at once (the
+    saturation throughput S), then Poisson arrivals at 0.5 S and 0.9 S with the
+    same request draws, reporting p50 / p99 latency (submit to result)."""
     import torch
     from paper_2404_02521_amd.serve import Server, run_poisson
     from synthetic import serving_requests
-    t, insts = serving_requests(rate, count, seed=seed, sides=sides)
+    _, insts = serving_requests(1.0, count, seed=seed, sides=sides)
+    out = {"workload": "%d requests, sides %s, N in {16,32,64}, T~U[0.25,2], LOD coarse "
+                       "propagator; saturation, then Poisson at 0.5x and 0.9x of it"
+                       % (count, list(sides))}
     sv = Server(64 << 30, max_resident=64, n_streams=8)
-    r = run_poisson(sv, t, insts)
+    r = run_poisson(sv, [0.0] * count, insts)
+    sat = r["solves_per_s"]
+    out["saturation"] = {"solves_per_s": round(sat, 2), "p50_ms": round(r["p50_ms"], 2),
+                         "p99_ms": round(r["p99_ms"], 2), "peak_resident": r["peak_resident"]}
+    for frac in (0.5, 0.9):
+        t, _ = serving_requests(frac * sat, count, seed=seed, sides=sides)
+        r = run_poisson(sv, t, insts)
+        out["poisson_%.1fx" % frac] = {"rate": round(frac * sat, 2),
+                                       "solves_per_s": round(r["solves_per_s"], 2),
+                                       "p50_ms": round(r["p50_ms"], 2),
+                                       "p99_ms": round(r["p99_ms"], 2),
+                                       "mean_iters": round(sum(r["iters"]) / count, 2),
+                                       "peak_resident": r["peak_resident"]}
     sv.close()
     torch.cuda.empty_cache()
-    return {"workload": "Poisson %.0f req/s, %d requests, sides %s, N in {16,32,64}, "
-                        "T~U[0.25,2]" % (rate, count, list(sides)),
-            "solves_per_s": round(r["solves_per_s"], 3), "p50_ms": round(r["p50_ms"], 2),
-            "p99_ms": round(r["p99_ms"], 2), "mean_iters": round(sum(r["iters"]) / count, 2),
-            "peak_resident": r["peak_resident"]}
+    return out
 
 
 def run_cpu_baseline(inst, K_gpu):
