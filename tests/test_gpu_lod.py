@@ -93,3 +93,19 @@ def test_lod_graph_replay(pr):
         r = s.solve()
         torch.cuda.synchronize()
         assert r.iters == e.iters and np.array_equal(host(r.value), host(e.value))
+
+
+def test_lod_max_size_2049(pr):
+    """One LOD step on the largest grid the line solver takes (2047 unknowns per
+    line, 2048-entry cyclic reduction) against the oracle's Thomas solves."""
+    from synthetic import largest_single
+    inst = largest_single().replace(n_slices=1, T=1e-3, fine_steps_per_slice=0,
+                                    coarse_steps_per_slice=1, fp32=False)
+    p = oproblem(inst)
+    u0 = oracle.payoff_grid(p)
+    say("lod max size 2049")
+    s = pr.Solver(inst, coarse_kind=pr.PR_G_LOD)
+    got = host(s.apply(pr.PR_OP_COARSE, 0, to_dev(u0)))
+    ref = oracle.lod(p, 1, inst.T, 0.0, u0)
+    assert abs_max(got, ref) <= 1e-12
+    s.close()

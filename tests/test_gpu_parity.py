@@ -214,3 +214,21 @@ def test_full_size_parareal_error_vs_serial(pr):
     err = rel_max(host(res.value), ser)
     assert res.iters >= 1
     assert err <= FP32_TOL, (res.iters, err)
+
+
+def test_max_size_fused_launch_2049(pr):
+    """The largest grid (2049^2) through exactly one prep step plus one 6-step
+    fused launch of the FP32 increment kernel, against the FP64 oracle; the
+    increment F(u) - u is checked on its own scale."""
+    from synthetic import largest_single
+    inst = largest_single().replace(n_slices=1, T=7e-6, fine_steps_per_slice=7,
+                                    coarse_steps_per_slice=1)
+    p = oproblem(inst)
+    u0 = oracle.payoff_grid(p)
+    say("max size 2049 fused launch")
+    s = pr.Solver(inst, coarse_kind=pr.PR_G_LOD)
+    got = host(s.apply(pr.PR_OP_FINE, 0, to_dev(u0)))
+    ref = oracle.fine(p, 7, inst.T / 7, 0.0, u0)
+    assert rel_max(got, ref) <= FP32_TOL
+    assert rel_max(got - u0, ref - u0) <= FP32_TOL
+    s.close()
