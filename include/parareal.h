@@ -215,7 +215,8 @@ pr_status parareal_attach_fno(pr_solver* s, pr_fno* f);
  * v0 at tau_slice and v1 at tau_{slice+1} (n*n doubles each, device).  Writes
  * four 64 x 64 FP32 planes (device) [w_in, B1, V_in, V_tgt]: w_in = R_s(v0 -
  * B(tau_slice)) with zero ring, B1 = the Coons patch of g(tau_{slice+1}) on the
- * 64 x 64 grid (base PR_FNO_BASE_LOD: plus the LOD prediction's w), V_in =
+ * 64 x 64 grid (base PR_FNO_BASE_LOD: plus the 64 x 64 LOD prediction's w;
+ * PR_FNO_BASE_FINE_LOD: plus R_s(LOD(v0) - B(tau_{slice+1})) of the fine LOD), V_in =
  * B0 + w_in and V_tgt = B1 + R_s(v1 - B(tau_{slice+1})) with the Coons B1. */
 pr_status parareal_fno_pair(pr_solver* s, int32_t slice, const double* v0, const double* v1,
                             int32_t base, float* pair_out);
@@ -340,8 +341,12 @@ enum { PR_FNO_FP32 = 0, PR_FNO_BF16 = 1 };
  *   PR_FNO_BASE_LOD      the LOD implicit propagator (PR_G_LOD's scheme) run on
  *                        the 64 x 64 grid itself over the slice (coarse_steps
  *                        steps, default 4) from B(tau_n) + w_in: the network
- *                        predicts the correction to that cheap, stable step. */
-enum { PR_FNO_BASE_ZERO = 0, PR_FNO_BASE_IDENTITY = 1, PR_FNO_BASE_LOD = 2 };
+ *                        predicts the correction to that cheap, stable step;
+ *   PR_FNO_BASE_FINE_LOD the LOD propagator on the fine grid itself (coarse_steps
+ *                        steps, default 1): G(u) = LOD(u) + P_s(out_scale * FNO(w)),
+ *                        the network predicts the restricted correction F - LOD. */
+enum { PR_FNO_BASE_ZERO = 0, PR_FNO_BASE_IDENTITY = 1, PR_FNO_BASE_LOD = 2,
+       PR_FNO_BASE_FINE_LOD = 3 };
 
 
 typedef struct {

@@ -24,7 +24,7 @@ PR_FLAG_TIME_STEPS = 1
 PR_FLAG_GRAPH = 2
 PR_FLAG_NO_FALLBACK = 4
 PR_FNO_FP32, PR_FNO_BF16 = 0, 1
-PR_FNO_BASE_ZERO, PR_FNO_BASE_IDENTITY, PR_FNO_BASE_LOD = 0, 1, 2
+PR_FNO_BASE_ZERO, PR_FNO_BASE_IDENTITY, PR_FNO_BASE_LOD, PR_FNO_BASE_FINE_LOD = 0, 1, 2, 3
 PR_FNO_GRID = 64
 PR_FNO_MAX_BATCH = 512
 

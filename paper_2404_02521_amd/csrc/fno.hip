@@ -969,7 +969,7 @@ pr_status pr_fno_create(const pr_fno_config* cfg, void* ws, uint64_t bytes, void
     if (!cfg || cfg->max_batch < 1 || cfg->max_batch > PR_FNO_MAX_BATCH) return PR_EINVAL;
     if (!valid_prec(cfg->precision)) return PR_EINVAL;
     if (!(cfg->out_scale > 0.0) || !std::isfinite(cfg->out_scale)) return PR_EINVAL;
-    if (cfg->base < PR_FNO_BASE_ZERO || cfg->base > PR_FNO_BASE_LOD) return PR_EINVAL;
+    if (cfg->base < PR_FNO_BASE_ZERO || cfg->base > PR_FNO_BASE_FINE_LOD) return PR_EINVAL;
     const Layout L = make_layout(cfg->max_batch);
     if (!ws || bytes < L.total) return PR_ENOMEM;
     if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0) return PR_EINVAL;

@@ -474,6 +474,16 @@ pr_status fno_lod_base(pr_solver* s, const double* wc, int n, double* wb) {
     return PR_OK;
 }
 
+// PR_FNO_BASE_FINE_LOD: out = the LOD propagator on the fine grid over slice n
+// (coarse_steps steps, default 1) from the interior state u.
+pr_status fno_fine_lod(pr_solver* s, const double* u, int n, double* out) {
+    const int m = s->opt.coarse_steps > 0 ? s->opt.coarse_steps : 1;
+    HIPCHK(launch_lod_slice(u, out, s->at<double>(s->L.lw0), s->at<double>(s->L.lw1),
+                            s->at<double>(s->L.lwb), s->fg, s->coef, s->bcf, s->dT / m,
+                            n * s->dT, m, s->stream));
+    return PR_OK;
+}
+
 // Neural G over slice n: gout = B(tau_{n+1}) + P_s(base + scale * FNO(wc, params)),
 // wc = R_s(U_n); the ring of gout is g(tau_{n+1}) by construction of B.
 pr_status fno_g(pr_solver* s, const double* Uall, int n, double* gout) {
@@ -483,13 +493,23 @@ pr_status fno_g(pr_solver* s, const double* Uall, int n, double* gout) {
     double* wo = s->at<double>(s->L.fwc1);
     double* Tp = s->at<double>(s->L.fTp);
     const double* Sp = s->at<double>(s->L.Sp);
-    pr_status r = fno_restrict(s, Uall + (long long)n * g.stride, n * s->dT, wc);
+    const double* u = Uall + (long long)n * g.stride;
+    pr_status r = fno_restrict(s, u, n * s->dT, wc);
     if (r != PR_OK) return r;
     float* fin = s->at<float>(s->L.fin);
     float* fmeta = s->at<float>(s->L.fmeta);
     float* fout = s->at<float>(s->L.fout);
     HIPCHK(launch_fno_in(wc, fin, fmeta, s->bcf, s->stream));
     HIPCHK(fno::infer(s->fno, fin, fmeta, 1, fout, s->stream));
+    if (fno::base(s->fno) == PR_FNO_BASE_FINE_LOD) {
+        // gout = LOD(u) on the fine grid, plus the prolonged correction
+        r = fno_fine_lod(s, u, n, gout);
+        if (r != PR_OK) return r;
+        HIPCHK(launch_fno_out(nullptr, fout, fno::out_scale(s->fno), wo, s->stream));
+        HIPCHK(fno::gemm_f64(Sp, mi, 1, wo, mi, 1, Tp, mi, nf, mi, mi, 0.0, s->stream));
+        HIPCHK(fno::gemm_f64(Tp, mi, 1, Sp, 1, mi, gout, g.pitch, nf, nf, mi, 1.0, s->stream));
+        return PR_OK;
+    }
     const double* base = nullptr;
     if (fno::base(s->fno) == PR_FNO_BASE_IDENTITY) base = wc;
     if (fno::base(s->fno) == PR_FNO_BASE_LOD) {
@@ -881,7 +901,7 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
             return PR_EDEVICE;
         }
     }
-    if (s->lod && lod_set_lds(s->fg.nin) != hipSuccess) {
+    if ((s->lod || s->fnog) && lod_set_lds(s->fg.nin) != hipSuccess) {
         delete s;
         return PR_EDEVICE;
     }
@@ -1023,7 +1043,7 @@ pr_status parareal_attach_fno(pr_solver* s, pr_fno* f) {
 pr_status parareal_fno_pair(pr_solver* s, int32_t slice, const double* v0, const double* v1,
                             int32_t base, float* pair_out) {
     if (!s || !v0 || !v1 || !pair_out) return PR_EINVAL;
-    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_LOD) return PR_EINVAL;
+    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_FINE_LOD) return PR_EINVAL;
     if (s->opt.coarse_kind != PR_G_FNO) {
         s->err = "the solver was not created with PR_G_FNO";
         return PR_EINVAL;
@@ -1036,10 +1056,18 @@ pr_status parareal_fno_pair(pr_solver* s, int32_t slice, const double* v0, const
     HIPCHK(launch_pack(v0, u, g, s->stream));
     pr_status r = fno_restrict(s, u, slice * s->dT, w0);
     if (r != PR_OK) return r;
+    double* wb = nullptr;
+    if (base == PR_FNO_BASE_FINE_LOD) {
+        double* lo = s->at<double>(s->L.Gf);   // one-slice temporary outside a solve
+        r = fno_fine_lod(s, u, slice, lo);
+        if (r != PR_OK) return r;
+        wb = s->at<double>(s->L.fwb);
+        r = fno_restrict(s, lo, (slice + 1) * s->dT, wb);
+        if (r != PR_OK) return r;
+    }
     HIPCHK(launch_pack(v1, u, g, s->stream));
     r = fno_restrict(s, u, (slice + 1) * s->dT, w1);
     if (r != PR_OK) return r;
-    double* wb = nullptr;
     if (base == PR_FNO_BASE_LOD) {
         wb = s->at<double>(s->L.fwb);
         r = fno_lod_base(s, w0, slice, wb);
@@ -1053,7 +1081,7 @@ pr_status parareal_fno_pair(pr_solver* s, int32_t slice, const double* v0, const
 
 pr_status parareal_fno_pairs(pr_solver* s, int32_t base, float* pairs_out) {
     if (!s || !pairs_out) return PR_EINVAL;
-    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_LOD) return PR_EINVAL;
+    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_FINE_LOD) return PR_EINVAL;
     if (s->opt.coarse_kind != PR_G_FNO) {
         s->err = "the solver was not created with PR_G_FNO";
         return PR_EINVAL;
@@ -1085,6 +1113,14 @@ pr_status parareal_fno_pairs(pr_solver* s, int32_t base, float* pairs_out) {
         if (base == PR_FNO_BASE_LOD) {
             wb = s->at<double>(s->L.fwb);
             r = fno_lod_base(s, w0, n, wb);
+            if (r != PR_OK) return r;
+        }
+        if (base == PR_FNO_BASE_FINE_LOD) {
+            double* lo = s->at<double>(s->L.tg);
+            r = fno_fine_lod(s, U + (long long)n * g.stride, n, lo);
+            if (r != PR_OK) return r;
+            wb = s->at<double>(s->L.fwb);
+            r = fno_restrict(s, lo, (n + 1) * s->dT, wb);
             if (r != PR_OK) return r;
         }
         HIPCHK(launch_pair(w0, w1, wb, pairs_out + (long long)n * 4 * 64 * 64, s->bcf,

@@ -57,11 +57,15 @@ def g_ref(pf, p, u, tau0, tau1, scale, base="identity"):
     inp[..., 5] = i[None, :, None]
     inp[..., 6] = i[None, None, :]
     out = ofno.forward(p, inp)[0]
+    P = ofno.sine_prolong_matrix(62, pf.M - 2)
+    if base == "fine_lod":
+        V = oracle.lod(pf, 1, tau1 - tau0, tau0, u)
+        V[1:-1, 1:-1] += P @ (scale * out[1:-1, 1:-1]) @ P.T
+        return V
     b = {"identity": wc, "zero": 0.0, "lod": None}[base]
     if base == "lod":
         b = lod_base_ref(pf, wc, tau0, tau1)
     wo = b + scale * out[1:-1, 1:-1]
-    P = ofno.sine_prolong_matrix(62, pf.M - 2)
     ring1 = oracle.set_boundary(pf, tau1, np.zeros((pf.M, pf.M)))
     B1 = ofno.coons(ring1, pf.M)
     V = B1.copy()
@@ -77,7 +81,7 @@ def pr():
     return pr_
 
 
-BASES = {"zero": 0, "identity": 1, "lod": 2}
+BASES = {"zero": 0, "identity": 1, "lod": 2, "fine_lod": 3}
 
 
 def make(pr, inst, flat, scale, base="identity", **kw):
@@ -90,7 +94,8 @@ def make(pr, inst, flat, scale, base="identity", **kw):
 
 
 @pytest.mark.parametrize("M,slice_,base", [(129, 0, "identity"), (131, 3, "identity"),
-                                           (129, 2, "lod"), (131, 0, "zero")])
+                                           (129, 2, "lod"), (131, 0, "zero"),
+                                           (129, 1, "fine_lod")])
 def test_fno_g_vs_oracle(pr, M, slice_, base):
     inst = plain_at_scale(2, M=M, n_slices=8, coarse_M=33)
     pf = oproblem(inst)
@@ -108,7 +113,7 @@ def test_fno_g_vs_oracle(pr, M, slice_, base):
     net.close()
 
 
-@pytest.mark.parametrize("base", ["identity", "lod"])
+@pytest.mark.parametrize("base", ["identity", "lod", "fine_lod"])
 def test_fno_pair_vs_oracle(pr, base):
     inst = plain_at_scale(4, M=129, n_slices=8, coarse_M=33)
     pf = oproblem(inst)
@@ -128,6 +133,8 @@ def test_fno_pair_vs_oracle(pr, base):
     B1 = ofno.coons(oracle.set_boundary(pc, 2 * dT, z), 64)
     pad = lambda a: np.pad(a, 1)
     b1 = B1 + (pad(lod_base_ref(pf, w0, dT, 2 * dT)) if base == "lod" else 0.0)
+    if base == "fine_lod":
+        b1 = B1 + pad(restrict_ref(pf, oracle.lod(pf, 1, dT, dT, u0), 2 * dT))
     ref = np.stack([pad(w0), b1, B0 + pad(w0), B1 + pad(w1)])
     for k in range(4):
         assert rel_max(got[k], ref[k]) <= 1e-6, k
