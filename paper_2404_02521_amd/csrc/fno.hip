@@ -139,18 +139,65 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
             for (int j = 0; j < TN; ++j) acc[i][j] = T(0);
     }
 
+    // 16-byte loads along a contiguous, aligned fast dimension (FP32 operands)
+    bool a_vec = false, b_vec = false;
+    if constexpr (std::is_same<T, float>::value) {
+        a_vec = a_kfast && (g.a.rs % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+        b_vec = b_nfast && (g.b.rs % 4 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    }
+
     for (int k0 = 0; k0 < g.K; k0 += KT) {
-        for (int e = tid; e < BM * KT; e += kThreads) {
-            int mm, kk;
-            if (a_kfast) { kk = e % KT; mm = e / KT; } else { mm = e % BM; kk = e / BM; }
-            const int m = m0 + mm, k = k0 + kk;
-            As[kk][mm] = (m < g.M && k < g.K) ? A[(long long)m * g.a.rs + (long long)k * g.a.cs] : T(0);
+        if (a_vec) {
+            for (int e = tid; e < BM * (KT / 4); e += kThreads) {
+                const int kk = (e % (KT / 4)) * 4, mm = e / (KT / 4);
+                const int m = m0 + mm, k = k0 + kk;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (m < g.M) {
+                    const float* src = reinterpret_cast<const float*>(A) + (long long)m * g.a.rs + k;
+                    if (k + 3 < g.K) {
+                        v = *reinterpret_cast<const float4*>(src);
+                    } else {
+                        if (k < g.K) v.x = src[0];
+                        if (k + 1 < g.K) v.y = src[1];
+                        if (k + 2 < g.K) v.z = src[2];
+                    }
+                }
+                As[kk][mm] = (T)v.x; As[kk + 1][mm] = (T)v.y;
+                As[kk + 2][mm] = (T)v.z; As[kk + 3][mm] = (T)v.w;
+            }
+        } else {
+            for (int e = tid; e < BM * KT; e += kThreads) {
+                int mm, kk;
+                if (a_kfast) { kk = e % KT; mm = e / KT; } else { mm = e % BM; kk = e / BM; }
+                const int m = m0 + mm, k = k0 + kk;
+                As[kk][mm] = (m < g.M && k < g.K) ? A[(long long)m * g.a.rs + (long long)k * g.a.cs] : T(0);
+            }
         }
-        for (int e = tid; e < KT * BN; e += kThreads) {
-            int kk, nn;
-            if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % KT; nn = e / KT; }
-            const int n = n0 + nn, k = k0 + kk;
-            Bs[kk][nn] = (n < g.N && k < g.K) ? B[(long long)k * g.b.rs + (long long)n * g.b.cs] : T(0);
+        if (b_vec) {
+            for (int e = tid; e < KT * (BN / 4); e += kThreads) {
+                const int nn = (e % (BN / 4)) * 4, kk = e / (BN / 4);
+                const int n = n0 + nn, k = k0 + kk;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k < g.K) {
+                    const float* src = reinterpret_cast<const float*>(B) + (long long)k * g.b.rs + n;
+                    if (n + 3 < g.N) {
+                        v = *reinterpret_cast<const float4*>(src);
+                    } else {
+                        if (n < g.N) v.x = src[0];
+                        if (n + 1 < g.N) v.y = src[1];
+                        if (n + 2 < g.N) v.z = src[2];
+                    }
+                }
+                Bs[kk][nn] = (T)v.x; Bs[kk][nn + 1] = (T)v.y;
+                Bs[kk][nn + 2] = (T)v.z; Bs[kk][nn + 3] = (T)v.w;
+            }
+        } else {
+            for (int e = tid; e < KT * BN; e += kThreads) {
+                int kk, nn;
+                if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % KT; nn = e / KT; }
+                const int n = n0 + nn, k = k0 + kk;
+                Bs[kk][nn] = (n < g.N && k < g.K) ? B[(long long)k * g.b.rs + (long long)n * g.b.cs] : T(0);
+            }
         }
         __syncthreads();
         if constexpr (MF) {
