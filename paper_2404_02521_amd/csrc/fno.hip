@@ -72,6 +72,7 @@ struct GemmArgs {
     long long bias_s;
     int M, N, K;
     int n1, n2;   // batch = n0 x n1 x n2, blockIdx.z = (i0 * n1 + i1) * n2 + i2
+    int ones_row; // row of A read as all ones (-1: none)
     T alpha, beta;
 };
 
@@ -142,7 +143,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
     // 16-byte loads along a contiguous, aligned fast dimension (FP32 operands)
     bool a_vec = false, b_vec = false;
     if constexpr (std::is_same<T, float>::value) {
-        a_vec = a_kfast && (g.a.rs % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+        a_vec = a_kfast && g.ones_row < 0 && (g.a.rs % 4 == 0) &&
+                ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
         b_vec = b_nfast && (g.b.rs % 4 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
     }
 
@@ -170,7 +172,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
                 int mm, kk;
                 if (a_kfast) { kk = e % KT; mm = e / KT; } else { mm = e % BM; kk = e / BM; }
                 const int m = m0 + mm, k = k0 + kk;
-                As[kk][mm] = (m < g.M && k < g.K) ? A[(long long)m * g.a.rs + (long long)k * g.a.cs] : T(0);
+                As[kk][mm] = (m < g.M && k < g.K)
+                                 ? (m == g.ones_row ? T(1) : A[(long long)m * g.a.rs + (long long)k * g.a.cs])
+                                 : T(0);
             }
         }
         if (b_vec) {
@@ -274,7 +278,7 @@ struct Gemm {
     GemmArgs<T> g{};
     int n0 = 1;
     Gemm(int M, int N, int K) {
-        g.M = M; g.N = N; g.K = K; g.n1 = 1; g.n2 = 1;
+        g.M = M; g.N = N; g.K = K; g.n1 = 1; g.n2 = 1; g.ones_row = -1;
         g.alpha = T(1); g.beta = T(0);
     }
     Gemm& A(const T* p, long long rs, long long cs, long long off = 0) {
@@ -297,6 +301,7 @@ struct Gemm {
     Gemm& bias(const T* p, long long s = 1) { g.bias = p; g.bias_s = s; return *this; }
     Gemm& act_out(T* d) { g.D = d; return *this; }
     Gemm& dact(const T* z) { g.Z = z; return *this; }
+    Gemm& ones(int row) { g.ones_row = row; return *this; }
 };
 
 template <typename T, int BM, int BN, bool MF>
@@ -596,7 +601,7 @@ Layout make_layout(int Bm) {
     L.gT = take((uint64_t)Bm * G * 2 * MX * C * f);
     L.gX = take((uint64_t)NMODE * Bm * 2 * C * f);
     L.gY = take((uint64_t)Bm * 2 * NMODE * C * f);
-    L.part = take((uint64_t)kSplits * 4096 * f);
+    L.part = take((uint64_t)kSplits * (C + 1) * PH * f);   // largest (K+1) x N: P1 and p1
     L.gpred = take(Q * f);
     L.cc = take(Q * f);
     L.lpart = take((uint64_t)Bm * G * 2 * 8);
@@ -706,9 +711,11 @@ hipError_t dense(pr_fno* f, const float* in, int K, const float* W, const float*
 }
 
 // gW (K x N) = in^T (K x Q) g (Q x N), written to dst; split over Q, then summed
-// in a fixed order.
+// in a fixed order.  bias: also the column sums of g, as row K (the flat
+// parameter vector keeps every bias block right after its weight block).
 hipError_t wgrad(pr_fno* f, const float* in, int K, const float* g, int N, float* dst,
-                 long long Q, bool mf) {
+                 long long Q, bool mf, bool bias = true) {
+    const int KB = bias ? K + 1 : K;   // rows of the product; row K reads ones
     const long long kc = (Q + kSplits - 1) / kSplits;
     const int S = (int)((Q + kc - 1) / kc);
     float* part = f->at(f->L.part);
@@ -716,41 +723,21 @@ hipError_t wgrad(pr_fno* f, const float* in, int K, const float* g, int N, float
     // splits and the tail separately
     const int full = (int)(Q / kc);
     if (full > 0) {
-        Gemm<float> a(K, N, (int)kc);
-        a.A(in, 1, K).B(g, N, 1).Cm(part, N, 1).batch(0, full, kc * K, kc * N, (long long)K * N);
+        Gemm<float> a(KB, N, (int)kc);
+        a.A(in, 1, K).B(g, N, 1).Cm(part, N, 1).batch(0, full, kc * K, kc * N, (long long)KB * N);
+        if (bias) a.ones(K);
         TRY(run(a, mf, f->st));
     }
     if (full < S) {
         const long long rem = Q - (long long)full * kc;
-        Gemm<float> a(K, N, (int)rem);
+        Gemm<float> a(KB, N, (int)rem);
         a.A(in, 1, K, (long long)full * kc * K).B(g, N, 1, (long long)full * kc * N)
-            .Cm(part, N, 1, (long long)full * K * N);
+            .Cm(part, N, 1, (long long)full * KB * N);
+        if (bias) a.ones(K);
         TRY(run(a, mf, f->st));
     }
-    Gemm<float> r(1, K * N, S);
-    r.A(f->ones, 0, 0).B(part, (long long)K * N, 1).Cm(dst, 0, 1);
-    return run(r, false, f->st);
-}
-
-// Column sums of g (Q x N) -> dst (N).
-hipError_t colsum(pr_fno* f, const float* g, int N, float* dst, long long Q) {
-    const long long kc = (Q + kSplits - 1) / kSplits;
-    const int S = (int)((Q + kc - 1) / kc);
-    const int full = (int)(Q / kc);
-    float* part = f->at(f->L.part);
-    if (full > 0) {
-        Gemm<float> a(1, N, (int)kc);
-        a.A(f->ones, 0, 0).B(g, N, 1).Cm(part, 0, 1).batch(0, full, 0, kc * N, N);
-        TRY(run(a, false, f->st));
-    }
-    if (full < S) {
-        const long long rem = Q - (long long)full * kc;
-        Gemm<float> a(1, N, (int)rem);
-        a.A(f->ones, 0, 0).B(g, N, 1, (long long)full * kc * N).Cm(part, 0, 1, (long long)full * N);
-        TRY(run(a, false, f->st));
-    }
-    Gemm<float> r(1, N, S);
-    r.A(f->ones, 0, 0).B(part, N, 1).Cm(dst, 0, 1);
+    Gemm<float> r(1, KB * N, S);
+    r.A(f->ones, 0, 0).B(part, (long long)KB * N, 1).Cm(dst, 0, 1);
     return run(r, false, f->st);
 }
 
@@ -909,16 +896,14 @@ hipError_t backward(pr_fno* f, const float* gout, int B, bool mf) {
     float* gA = f->at(f->L.gA);
     float* gB = f->at(f->L.gB);
     // projection
-    TRY(wgrad(f, f->at(f->L.hq), PH, gout, 1, Gd + pi.P2, Q, mf));
-    TRY(colsum(f, gout, 1, Gd + pi.p2, Q));
+    TRY(wgrad(f, f->at(f->L.hq), PH, gout, 1, Gd + pi.P2, Q, mf));   // and p2
     {   // gzq = gout P2^T * GELU'(zq)
         Gemm<float> q((int)Q, PH, 1);
         q.A(gout, 1, 0).B(P + pi.P2, 0, 1).Cm(gbig, PH, 1).dact(f->at(f->L.zq));
         TRY(run(q, false, f->st));
     }
     const float* v4 = f->at(f->L.zz[NL - 1]);
-    TRY(wgrad(f, v4, C, gbig, PH, Gd + pi.P1, Q, mf));
-    TRY(colsum(f, gbig, PH, Gd + pi.p1, Q));
+    TRY(wgrad(f, v4, C, gbig, PH, Gd + pi.P1, Q, mf));   // and p1
     {   // gv4 = gzq P1^T (no activation after the last layer)
         Gemm<float> q((int)Q, C, PH);
         q.A(gbig, PH, 1).B(P + pi.P1, 1, PH).Cm(gA, C, 1);
@@ -927,8 +912,7 @@ hipError_t backward(pr_fno* f, const float* gout, int B, bool mf) {
     // layers: gA holds dL/dz_l on entry
     for (int l = NL - 1; l >= 0; --l) {
         const float* v = f->at(f->L.vv[l]);
-        TRY(wgrad(f, v, C, gA, C, Gd + pi.W[l], Q, mf));
-        TRY(colsum(f, gA, C, Gd + pi.b[l], Q));
+        TRY(wgrad(f, v, C, gA, C, Gd + pi.W[l], Q, mf));   // and b_l
         TRY(spectral_bwd(f, l, gA, gB, B, mf));
         // gB += gA W^T, times GELU'(z_{l-1}) when v_l = GELU(z_{l-1})
         Gemm<float> q((int)Q, C, C);
@@ -938,15 +922,13 @@ hipError_t backward(pr_fno* f, const float* gout, int B, bool mf) {
         std::swap(gA, gB);
     }
     // lift: gA = dL/dv0
-    TRY(wgrad(f, f->at(f->L.h1), LH, gA, C, Gd + pi.L2, Q, mf));
-    TRY(colsum(f, gA, C, Gd + pi.l2, Q));
+    TRY(wgrad(f, f->at(f->L.h1), LH, gA, C, Gd + pi.L2, Q, mf));   // and l2
     {   // gz1 = gv0 L2^T * GELU'(z1)
         Gemm<float> q((int)Q, LH, C);
         q.A(gA, C, 1).B(P + pi.L2, 1, C).Cm(gbig, LH, 1).dact(f->at(f->L.z1));
         TRY(run(q, mf, f->st));
     }
-    TRY(wgrad(f, f->at(f->L.inp), CIN, gbig, LH, Gd + pi.L1, Q, mf));
-    TRY(colsum(f, gbig, LH, Gd + pi.l1, Q));
+    TRY(wgrad(f, f->at(f->L.inp), CIN, gbig, LH, Gd + pi.L1, Q, mf));   // and l1
     return hipSuccess;
 }
 
