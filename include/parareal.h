@@ -85,10 +85,13 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
                               term, then tridiagonal x lines and y lines (Sec. 3.2's
                               coarse propagator is implicit Euler with a larger step) */ };
 
-/* Option flags.  PR_FLAG_TIME_STEPS: bracket every explicit fine-step launch
- * with HIP events on the solver's stream and report their summed durations in
- * pr_stats.t_step_kernels_ms (otherwise the field brackets the whole run of
- * step launches, gaps included). */
+/* Option flags.  PR_FLAG_TIME_STEPS: bracket every 8th explicit fine-step
+ * launch of each sweep (the first included) with HIP events on the solver's
+ * stream and report their summed durations in pr_stats.t_step_kernels_ms, their
+ * number and algorithmic bytes in timed_step_launches / timed_step_bytes
+ * (without the flag the field brackets the whole run of step launches, gaps
+ * included).  The launches of one sweep all have the same shape, so the sample
+ * gives their average duration at an eighth of the event cost. */
 #define PR_FLAG_TIME_STEPS 1u
 /* PR_FLAG_GRAPH: capture the initial sweep and each Parareal iteration k (its
  * fine sweep, coarse chain, correction and norm) into a HIP graph once, on a
@@ -159,6 +162,8 @@ typedef struct {
     uint64_t workspace_bytes;   /* bytes of workspace the solver uses */
     int32_t coarse_fallback;    /* 1 when PR_G_FNO fell back to PR_G_LOD in this solve */
     int32_t pad_;
+    int64_t timed_step_launches; /* step launches bracketed by events (PR_FLAG_TIME_STEPS) */
+    double timed_step_bytes;     /* their algorithmic bytes (t_step_kernels_ms covers them) */
 } pr_stats;
 
 /* Explicit-Euler stability bound and the planned step counts (host only, no

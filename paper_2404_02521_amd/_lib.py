@@ -59,7 +59,8 @@ class pr_stats(C.Structure):
                 ("fine_point_steps", C.c_int64), ("fine_step_launches", C.c_int64),
                 ("fine_step_bytes", C.c_double), ("t_step_kernels_ms", C.c_double),
                 ("workspace_bytes", C.c_uint64), ("coarse_fallback", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("pad_", C.c_int32), ("timed_step_launches", C.c_int64),
+                ("timed_step_bytes", C.c_double)]
 
 
 class pr_server_options(C.Structure):

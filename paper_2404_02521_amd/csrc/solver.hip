@@ -219,6 +219,9 @@ struct pr_solver {
     int min_rows = 8;                  // shortest row chunk of a step launch (PR_STEP_MINROWS)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
     std::map<int, double> graph_bytes;
+    int ev_every = 8;                  // PR_FLAG_TIME_STEPS: time every ev_every-th launch
+    int64_t timed_launches = 0;        // launches bracketed by events in this call
+    double timed_bytes = 0;            // their algorithmic bytes
     int64_t sweep_launches = 0;        // step launches of the last fine_sweep
     double sweep_bytes = 0;            // their algorithmic bytes
     bool graph = false;                // PR_FLAG_GRAPH
@@ -298,15 +301,19 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         for (int q = 1; q < s->mF;) {
             const int S = std::min(s->fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
-            const bool tv = step_ms && s->step_ev_used + 2 <= (int)s->step_ev.size();
+            const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
+                            s->step_ev_used + 2 <= (int)s->step_ev.size();
             if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
             HIPCHK(launch_fine_tb_f32(A, Lb, B, b, S, s->stream));
+            const double bytes = 12.0 * S * (double)count * g.nin * g.nin;
             if (tv) {
                 HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
                 s->step_ev_used += 2;
+                s->timed_launches += 1;
+                s->timed_bytes += bytes;
             }
             s->sweep_launches += 1;
-            s->sweep_bytes += 12.0 * S * (double)count * g.nin * g.nin;
+            s->sweep_bytes += bytes;
             std::swap(A, B);
             q += S;
         }
@@ -321,16 +328,20 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         for (int q = 0; q < s->mF;) {
             const int S = std::min(s->fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
-            const bool tv = step_ms && s->step_ev_used + 2 <= (int)s->step_ev.size();
+            const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
+                            s->step_ev_used + 2 <= (int)s->step_ev.size();
             if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
             HIPCHK(launch_fine_tb_f64(q == 0 ? Ubase + (long long)first * g.stride : A,
                                       q == 0 ? A : B, b, S, s->stream));
+            const double bytes = 16.0 * S * (double)count * g.nin * g.nin;
             if (tv) {
                 HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
                 s->step_ev_used += 2;
+                s->timed_launches += 1;
+                s->timed_bytes += bytes;
             }
             s->sweep_launches += 1;
-            s->sweep_bytes += 16.0 * S * (double)count * g.nin * g.nin;
+            s->sweep_bytes += bytes;
             if (q > 0) std::swap(A, B);
             q += S;
         }
@@ -673,6 +684,8 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
         return PR_EMODEL;
     }
     bool diverging = false;   // PR_G_FNO: non-finite, or two increments in a row growing
+    s->timed_launches = 0;
+    s->timed_bytes = 0;
     double* Ucur = s->U(0);
     double* Unext = s->U(1);
     double t_fine = 0, t_chain = 0, t_corr = 0, t_steps = 0, step_bytes = 0;
@@ -763,6 +776,8 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
         st->t_chain_ms = t_chain;
         st->t_correct_ms = t_corr;
         st->t_step_kernels_ms = t_steps;
+        st->timed_step_launches = s->timed_launches;
+        st->timed_step_bytes = s->timed_bytes;
         st->fine_point_steps = psteps;
         st->fine_step_launches = launches;
         st->fine_step_bytes = step_bytes;
@@ -893,6 +908,7 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     if (const char* e = std::getenv("PR_STEP_ROWS")) s->rows_override = std::atoi(e);
     if (const char* e = std::getenv("PR_STEP_FUSE")) s->fuse = std::max(1, std::min(8, std::atoi(e)));
     if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
+    if (const char* e = std::getenv("PR_STEP_TIME_EVERY")) s->ev_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_MINROWS")) s->min_rows = std::max(1, std::atoi(e));
     if (!s->fineg) {
         hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));

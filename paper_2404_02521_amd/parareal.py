@@ -28,7 +28,8 @@ def _stats_dict(st: L.pr_stats) -> dict:
                 t_correct_ms=st.t_correct_ms, fine_point_steps=st.fine_point_steps,
                 fine_step_launches=st.fine_step_launches, fine_step_bytes=st.fine_step_bytes,
                 t_step_kernels_ms=st.t_step_kernels_ms, workspace_bytes=st.workspace_bytes,
-                coarse_fallback=st.coarse_fallback)
+                coarse_fallback=st.coarse_fallback, timed_step_launches=st.timed_step_launches,
+                timed_step_bytes=st.timed_step_bytes)
 
 
 def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
