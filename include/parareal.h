@@ -396,11 +396,12 @@ pr_status pr_fno_loss(pr_fno* f, const float* pred, const float* pairs, const fl
  * gradients; step counts from 1. */
 pr_status pr_fno_adam(pr_fno* f, double lr, int32_t step);
 /* Forward, loss (scale = out_scale), backward and Adam on the pairs
- * idx[0..batch) (device int32 indices into pairs (N x 4 x 64 x 64) and meta
- * (N x 4)).  host_loss as in pr_fno_loss. */
-pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, const int32_t* idx,
-                            int32_t batch, double dT, double lam, double lr, int32_t step,
-                            int32_t precision, double* host_loss);
+ * idx[0..batch) (device int32 indices into pairs (n_pairs x 4 x 64 x 64) and
+ * meta (n_pairs x 4); an index outside [0, n_pairs) is clamped into it).
+ * host_loss as in pr_fno_loss. */
+pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, int64_t n_pairs,
+                            const int32_t* idx, int32_t batch, double dT, double lam, double lr,
+                            int32_t step, int32_t precision, double* host_loss);
 pr_status pr_fno_destroy(pr_fno* f);
 const char* pr_fno_last_error(const pr_fno* f);
 

@@ -125,9 +125,9 @@ SIGNATURES = [
                               C.c_double, C.c_double, C.c_double, C.c_void_p,
                               C.POINTER(C.c_double)]),
     ("pr_fno_adam", C.c_int, [C.c_void_p, C.c_double, C.c_int32]),
-    ("pr_fno_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
-                                    C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
-                                    C.POINTER(C.c_double)]),
+    ("pr_fno_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                    C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                    C.c_int32, C.POINTER(C.c_double)]),
     ("pr_fno_destroy", C.c_int, [C.c_void_p]),
     ("pr_fno_last_error", C.c_char_p, [C.c_void_p]),
 ]

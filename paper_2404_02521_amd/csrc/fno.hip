@@ -346,14 +346,14 @@ static hipError_t run(const Gemm<T>& q, bool mfma, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Network input of sample b: channels [w, s1, s2, rho, r, x/63, y/63].
 // w of sample b at w + src(b)*wstride, its parameters at meta + src(b)*4,
-// src(b) = idx ? idx[b] : b.
+// src(b) = idx ? idx[b] (clamped to [0, nsrc)) : b.
 __global__ void k_input(const float* __restrict__ w, long long wstride,
-                        const float* __restrict__ meta, const int* __restrict__ idx,
+                        const float* __restrict__ meta, const int* __restrict__ idx, int nsrc,
                         float* __restrict__ inp, int B) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)B * GG) return;
     const int b = (int)(t / GG), p = (int)(t % GG);
-    const int sb = idx ? idx[b] : b;
+    const int sb = idx ? min(max(idx[b], 0), nsrc - 1) : b;
     const float* mt = meta + (long long)sb * 4;
     float* o = inp + t * CIN;
     o[0] = w[(long long)sb * wstride + p];
@@ -403,6 +403,7 @@ struct LossArgs {
     const float* pairs;
     const float* meta;
     const int* idx;
+    int nsrc;      // pairs addressable through idx (indices are clamped to [0, nsrc))
     float* gpred;
     float* cc;
     double* part;
@@ -419,7 +420,7 @@ __device__ inline double v1_at(const LossArgs& a, const float* pr, const float* 
 
 __global__ __launch_bounds__(64) void k_loss1(LossArgs a) {
     const int b = blockIdx.x / G, x = blockIdx.x % G, y = threadIdx.x;
-    const int sb = a.idx ? a.idx[b] : b;
+    const int sb = a.idx ? min(max(a.idx[b], 0), a.nsrc - 1) : b;
     const float* pr = a.pairs + (long long)sb * 4 * GG;
     const float* ob = a.out + (long long)b * GG;
     const float* mt = a.meta + (long long)sb * 4;
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(64) void k_loss1(LossArgs a) {
 // nine-point stencil of every interior centre), mask the ring, scale.
 __global__ __launch_bounds__(64) void k_loss2(LossArgs a) {
     const int b = blockIdx.x / G, x = blockIdx.x % G, y = threadIdx.x;
-    const int sb = a.idx ? a.idx[b] : b;
+    const int sb = a.idx ? min(max(a.idx[b], 0), a.nsrc - 1) : b;
     const float* mt = a.meta + (long long)sb * 4;
     const double s1 = mt[0], s2 = mt[1], rho = mt[2], r = mt[3];
     const float* cb = a.cc + (long long)b * GG;
@@ -863,12 +864,12 @@ hipError_t spectral_bwd(pr_fno* f, int l, const float* gz, float* gv, int B, boo
 }
 
 hipError_t forward(pr_fno* f, const float* w, long long wstride, const float* meta, const int* idx,
-                   int B, bool mf, float* out) {
+                   int nsrc, int B, bool mf, float* out) {
     TRY(ensure_stacked(f));
     const long long Q = (long long)B * GG;
     float* inp = f->at(f->L.inp);
     hipLaunchKernelGGL(k_input, dim3(blocks_for(Q, 256)), dim3(256), 0, f->st, w, wstride, meta, idx,
-                       inp, B);
+                       nsrc, inp, B);
     TRY(hipGetLastError());
     const float* P = f->params;
     const ParamIndex& pi = f->pi;
@@ -933,8 +934,8 @@ hipError_t backward(pr_fno* f, const float* gout, int B, bool mf) {
 }
 
 hipError_t loss(pr_fno* f, const float* out, const float* pairs, const float* meta, const int* idx,
-                int B, double scale, double dT, double lam) {
-    LossArgs a{out, pairs, meta, idx, f->at(f->L.gpred), f->at(f->L.cc),
+                int nsrc, int B, double scale, double dT, double lam) {
+    LossArgs a{out, pairs, meta, idx, nsrc, f->at(f->L.gpred), f->at(f->L.cc),
                f->at<double>(f->L.lpart), B, scale, dT, lam, f->skip};
     hipLaunchKernelGGL(k_loss1, dim3(B * G), dim3(64), 0, f->st, a);
     hipLaunchKernelGGL(k_loss2, dim3(B * G), dim3(64), 0, f->st, a);
@@ -964,7 +965,7 @@ namespace fno {
 hipError_t infer(pr_fno* f, const float* w, const float* meta, int B, float* out, hipStream_t st) {
     hipStream_t keep = f->st;
     f->st = st;
-    hipError_t e = forward(f, w, GG, meta, nullptr, B, f->infer_prec == PR_FNO_BF16, out);
+    hipError_t e = forward(f, w, GG, meta, nullptr, 0, B, f->infer_prec == PR_FNO_BF16, out);
     f->st = keep;
     return e;
 }
@@ -1061,7 +1062,7 @@ pr_status pr_fno_forward(pr_fno* f, const float* w, const float* meta, int32_t b
     if (!f) return PR_EINVAL;
     if (!w || !meta || !out || batch < 1 || batch > f->Bm) return fail(f, PR_EINVAL, "bad forward arguments");
     if (!valid_prec(precision)) return fail(f, PR_EINVAL, "unknown precision");
-    FNO_HIP(forward(f, w, GG, meta, nullptr, batch, precision == PR_FNO_BF16, out));
+    FNO_HIP(forward(f, w, GG, meta, nullptr, 0, batch, precision == PR_FNO_BF16, out));
     f->fwd_batch = batch;
     f->fwd_prec = precision;
     return PR_OK;
@@ -1081,7 +1082,7 @@ pr_status pr_fno_loss(pr_fno* f, const float* pred, const float* pairs, const fl
     if (!f) return PR_EINVAL;
     if (!pred || !pairs || !meta || batch < 1 || batch > f->Bm || !(dT > 0.0) || !(lam >= 0.0))
         return fail(f, PR_EINVAL, "bad loss arguments");
-    FNO_HIP(loss(f, pred, pairs, meta, nullptr, batch, scale, dT, lam));
+    FNO_HIP(loss(f, pred, pairs, meta, nullptr, 0, batch, scale, dT, lam));
     if (gpred)
         FNO_HIP(hipMemcpyAsync(gpred, f->at(f->L.gpred), (size_t)batch * GG * sizeof(float),
                                hipMemcpyDeviceToDevice, f->st));
@@ -1100,18 +1101,19 @@ pr_status pr_fno_adam(pr_fno* f, double lr, int32_t step) {
     return PR_OK;
 }
 
-pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, const int32_t* idx,
-                            int32_t batch, double dT, double lam, double lr, int32_t step,
+pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, int64_t n_pairs,
+                            const int32_t* idx, int32_t batch, double dT, double lam, double lr, int32_t step,
                             int32_t precision, double* host_loss) {
     if (!f) return PR_EINVAL;
-    if (!pairs || !meta || !idx || batch < 1 || batch > f->Bm || !(dT > 0.0) || !(lam >= 0.0) ||
+    if (!pairs || !meta || !idx || n_pairs < 1 || n_pairs > INT32_MAX || batch < 1 ||
+        batch > f->Bm || !(dT > 0.0) || !(lam >= 0.0) ||
         step < 1 || !(lr >= 0.0))
         return fail(f, PR_EINVAL, "bad train-step arguments");
     if (!valid_prec(precision)) return fail(f, PR_EINVAL, "unknown precision");
     const bool mf = precision == PR_FNO_BF16;
     float* out = f->at(f->L.out);
-    FNO_HIP(forward(f, pairs, 4LL * GG, meta, idx, batch, mf, out));
-    FNO_HIP(loss(f, out, pairs, meta, idx, batch, f->out_scale, dT, lam));
+    FNO_HIP(forward(f, pairs, 4LL * GG, meta, idx, (int)n_pairs, batch, mf, out));
+    FNO_HIP(loss(f, out, pairs, meta, idx, (int)n_pairs, batch, f->out_scale, dT, lam));
     FNO_HIP(backward(f, f->at(f->L.gpred), batch, mf));
     FNO_HIP(adam(f, lr, step));
     f->fwd_batch = 0;

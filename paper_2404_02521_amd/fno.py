@@ -121,9 +121,11 @@ class Fno:
         import torch
         B = idx.shape[0]
         res = (C.c_double * 3)()
+        assert pairs.shape[0] == meta.shape[0], (pairs.shape, meta.shape)
         _check(L.lib().pr_fno_train_step(self.handle, _ptr(pairs, torch.float32),
-                                         _ptr(meta, torch.float32), _ptr(idx, torch.int32), B, dT,
-                                         lam, lr, step, precision, res if want_loss else None),
+                                         _ptr(meta, torch.float32), pairs.shape[0],
+                                         _ptr(idx, torch.int32), B, dT, lam, lr, step, precision,
+                                         res if want_loss else None),
                "pr_fno_train_step", self.handle)
         return (res[0], res[1], res[2]) if want_loss else None
 

@@ -121,3 +121,39 @@ def test_workspace_size_formula():
     big = largest_single()
     g, _, _, o = make_structs(big.replace(coarse_M=129))
     assert L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o)) < 40e9
+
+
+def test_fno_host_side_validation():
+    """pr_fno_* argument checks that run before any GPU call."""
+    lib = L.lib()
+    assert lib.pr_fno_param_count() == 2370465
+    assert lib.pr_fno_workspace_bytes(0) == 0
+    assert lib.pr_fno_workspace_bytes(L.PR_FNO_MAX_BATCH + 1) == 0
+    small, big = lib.pr_fno_workspace_bytes(1), lib.pr_fno_workspace_bytes(64)
+    assert 0 < small < big
+    h = C.c_void_p()
+    bad = [L.pr_fno_config(0, L.PR_FNO_FP32, 1.0, L.PR_FNO_BASE_IDENTITY, 0),
+           L.pr_fno_config(1, 7, 1.0, L.PR_FNO_BASE_IDENTITY, 0),
+           L.pr_fno_config(1, L.PR_FNO_FP32, 0.0, L.PR_FNO_BASE_IDENTITY, 0),
+           L.pr_fno_config(1, L.PR_FNO_FP32, 1.0, 9, 0)]
+    for cfg in bad:
+        assert lib.pr_fno_create(C.byref(cfg), None, 0, None, C.byref(h)) == L.PR_EINVAL
+    ok = L.pr_fno_config(1, L.PR_FNO_FP32, 1.0, L.PR_FNO_BASE_FINE_LOD, 0)
+    assert lib.pr_fno_create(C.byref(ok), None, 0, None, C.byref(h)) == L.PR_ENOMEM
+    assert lib.pr_fno_create(C.byref(ok), C.c_void_p(256), small - 1, None,
+                             C.byref(h)) == L.PR_ENOMEM
+    assert lib.pr_fno_forward(None, None, None, 1, 0, None) == L.PR_EINVAL
+    assert lib.pr_fno_destroy(None) == L.PR_EINVAL
+
+
+def test_fno_coarse_kind_validation():
+    """PR_G_FNO needs n >= 64; the server refuses it (requests carry no operator)."""
+    inst = plain_at_scale(0, M=33, n_slices=8, coarse_M=9)
+    g, m, p, o = make_structs(inst, L.PR_G_FNO)
+    assert L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o)) == 0
+    inst = plain_at_scale(0, M=129, n_slices=8, coarse_M=33)
+    g, m, p, o = make_structs(inst, L.PR_G_FNO)
+    assert L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o)) > 0
+    rid = C.c_int64()
+    assert L.lib().pr_server_submit(C.c_void_p(1), C.byref(g), C.byref(m), C.byref(p), C.byref(o),
+                                    C.c_void_p(1), C.byref(rid)) == L.PR_EMODEL
