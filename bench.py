@@ -413,6 +413,14 @@ def serving_leg(pr, count=120, seed=11, sides=(129, 257)):
                                        "p99_ms": round(r["p99_ms"], 2),
                                        "mean_iters": round(sum(r["iters"]) / count, 2),
                                        "peak_resident": r["peak_resident"]}
+    # the full grid-size mix at saturation only: 1025^2 requests take seconds each
+    _, full = serving_requests(1.0, 32, seed=seed + 1, sides=(129, 257, 513, 1025))
+    r = run_poisson(sv, [0.0] * len(full), full)
+    out["full_mix_saturation"] = {"sides": [129, 257, 513, 1025], "count": len(full),
+                                  "solves_per_s": round(r["solves_per_s"], 3),
+                                  "p50_ms": round(r["p50_ms"], 1), "p99_ms": round(r["p99_ms"], 1),
+                                  "peak_resident": r["peak_resident"],
+                                  "peak_arena_gb": round(r["peak_arena_bytes"] / 2 ** 30, 2)}
     sv.close()
     torch.cuda.empty_cache()
     return out
