@@ -259,32 +259,37 @@ def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
 
 def graph_leg(pr, reps=5):
     """hipGraph replay of whole Parareal iterations (PR_FLAG_GRAPH) against eager
-    launches on a launch-bound shape: 129^2, N = 64, same-grid implicit G, seeds
-    0-3; median of `reps` solves each after a warm-up solve (which captures)."""
+    launches: the 65^2 FP64 configuration (numerical G 33^2, N = 8; every kernel a
+    few microseconds, so launch cost dominates) and a 129^2 FP32 one (N = 64,
+    same-grid implicit G, seeds 0-3).  Median of `reps` solves each after a
+    warm-up solve (which captures)."""
     import statistics
     import torch
-    from synthetic import plain_at_scale
-    res = {}
-    for name, flags in (("eager", 0), ("graph", pr.PR_FLAG_GRAPH)):
-        ms, iters = [], []
-        for seed in range(4):
-            inst = plain_at_scale(seed, M=129, n_slices=64, coarse_M=33)
-            sv = pr.Solver(inst.replace(coarse_steps_per_slice=4), coarse_kind=pr.PR_G_LOD,
-                           flags=flags)
-            sv.solve()
-            torch.cuda.synchronize()
-            t = []
-            for _ in range(reps):
-                a = time.perf_counter()
-                r = sv.solve()
-                t.append((time.perf_counter() - a) * 1e3)
-            ms.append(statistics.median(t))
-            iters.append(r.iters)
-            sv.close()
-        res[name] = {"median_ms": [round(x, 3) for x in ms], "iters": iters}
-    res["speedup"] = round(sum(res["eager"]["median_ms"]) / sum(res["graph"]["median_ms"]), 3)
-    res["workload"] = ("129^2 FP32, N=64, LOD coarse propagator (4 steps per slice), seeds 0-3: "
-                       "eager launches vs one captured graph per iteration")
+    from synthetic import plain_at_scale, plain_fp64
+    cases = {"fp64_65": [(plain_fp64(), pr.PR_G_NUMERICAL)],
+             "fp32_129_lod": [(plain_at_scale(s, M=129, n_slices=64, coarse_M=33)
+                               .replace(coarse_steps_per_slice=4), pr.PR_G_LOD) for s in range(4)]}
+    res = {"workload": "eager launches vs one captured graph per Parareal iteration: "
+                       "65^2 FP64 (numerical G 33^2, N=8) and 129^2 FP32 (LOD G, N=64, seeds 0-3)"}
+    for case, items in cases.items():
+        row = {}
+        for name, flags in (("eager", 0), ("graph", pr.PR_FLAG_GRAPH)):
+            ms, iters = [], []
+            for inst, kind in items:
+                sv = pr.Solver(inst, coarse_kind=kind, flags=flags)
+                sv.solve()
+                torch.cuda.synchronize()
+                t = []
+                for _ in range(reps):
+                    a = time.perf_counter()
+                    r = sv.solve()
+                    t.append((time.perf_counter() - a) * 1e3)
+                ms.append(statistics.median(t))
+                iters.append(r.iters)
+                sv.close()
+            row[name] = {"median_ms": [round(x, 3) for x in ms], "iters": iters}
+        row["speedup"] = round(sum(row["eager"]["median_ms"]) / sum(row["graph"]["median_ms"]), 3)
+        res[case] = row
     return res
 
 
@@ -326,7 +331,7 @@ def fno_flops_per_sample():
 
 
 def fno_leg(pr, insts, seeds, serial_ref, train_s, parareal=True):
-    """Neural coarse propagator: pairs from serial F on 48 seed-drawn 257^2
+    """Neural coarse propagator: 20,032 pairs from serial F on 313 seed-drawn 257^2
     trajectories (N = 64, T = 1), BF16 training for a fixed budget, then Parareal
     with the trained operator as G on the bench instances (LOD fallback on)."""
     import torch
@@ -336,7 +341,7 @@ def fno_leg(pr, insts, seeds, serial_ref, train_s, parareal=True):
     from synthetic import plain_at_scale
     dT = 1.0 / 64
     t = time.perf_counter()
-    pairs, meta = generate_pairs([plain_at_scale(1000 + i, M=257) for i in range(48)])
+    pairs, meta = generate_pairs([plain_at_scale(1000 + i, M=257) for i in range(313)])
     vp, vm = generate_pairs([plain_at_scale(2000 + i, M=257) for i in range(4)])
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t
@@ -372,7 +377,7 @@ def fno_leg(pr, insts, seeds, serial_ref, train_s, parareal=True):
         sv.close()
         fi.close()
     return {"workload": "FNO width 32, 4 layers, 12x12 modes, 64^2, BF16 MFMA training on %d pairs "
-                        "(48 seed-drawn 257^2 F trajectories, N=64) for %.0f s; then G on the "
+                        "(313 seed-drawn 257^2 F trajectories, N=64) for %.0f s; then G on the "
                         "513^2 bench instances through DST transfers" % (pairs.shape[0], train_s),
             "data_s": round(t_data, 2), "train_steps": steps, "train_s": round(t_train, 2),
             "train_samples_per_s": round(64 * steps / t_train, 1),
