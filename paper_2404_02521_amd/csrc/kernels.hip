@@ -423,21 +423,37 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
         T* nxt = buf1;
         for (int st = first; st < a.steps; ++st) {
             if (nr > 0) {
-                T upl = cur[(I0 - 1) * nc + J - 1], up = cur[(I0 - 1) * nc + J],
-                  upr = cur[(I0 - 1) * nc + J + 1];
-                T cl = cur[I0 * nc + J - 1], c = cur[I0 * nc + J], cr = cur[I0 * nc + J + 1];
-                for (int r = 0; r < nr; ++r) {
+                // three-row window in slots 0..2 (row I in slot (I - I0 + 2) % 3 after
+                // it is loaded); the loop is unrolled by 3 so rotating it costs no moves
+                T wl[3], wc[3], wr[3];
+                wl[0] = cur[(I0 - 1) * nc + J - 1]; wc[0] = cur[(I0 - 1) * nc + J];
+                wr[0] = cur[(I0 - 1) * nc + J + 1];
+                wl[1] = cur[I0 * nc + J - 1]; wc[1] = cur[I0 * nc + J]; wr[1] = cur[I0 * nc + J + 1];
+                auto row = [&](int r, auto Uc, auto Cc, auto Dc) __attribute__((always_inline)) {
+                    constexpr int U = decltype(Uc)::value, Cs = decltype(Cc)::value,
+                                  D = decltype(Dc)::value;
                     const int I = I0 + r;
-                    const T dnl = cur[(I + 1) * nc + J - 1], dn = cur[(I + 1) * nc + J],
-                            dnr = cur[(I + 1) * nc + J + 1];
+                    wl[D] = cur[(I + 1) * nc + J - 1];
+                    wc[D] = cur[(I + 1) * nc + J];
+                    wr[D] = cur[(I + 1) * nc + J + 1];
                     const T* w = tab + 4 * I;
                     const T wd = w[2] + b2J, G = w[3] * fJ;
-                    const T L = w[0] * dn + w[1] * up + cpJ * cr + cmJ * cl +
-                                G * (dnr + upl - dnl - upr) - wd * c;
+                    const T c = wc[Cs];
+                    const T L = w[0] * wc[D] + w[1] * wc[U] + cpJ * wr[Cs] + cmJ * wl[Cs] +
+                                G * (wr[D] + wl[U] - wl[D] - wr[U]) - wd * c;
                     nxt[I * nc + J] = FP32 ? c + dt * ((T)lbc[I * nc + J] + L) : c + dt * L;
-                    upl = cl; up = c; upr = cr;
-                    cl = dnl; c = dn; cr = dnr;
+                };
+                using K0 = std::integral_constant<int, 0>;
+                using K1 = std::integral_constant<int, 1>;
+                using K2 = std::integral_constant<int, 2>;
+                int r = 0;
+                for (; r + 2 < nr; r += 3) {
+                    row(r, K0{}, K1{}, K2{});
+                    row(r + 1, K1{}, K2{}, K0{});
+                    row(r + 2, K2{}, K0{}, K1{});
                 }
+                if (r < nr) row(r, K0{}, K1{}, K2{});
+                if (r + 1 < nr) row(r + 1, K1{}, K2{}, K0{});
             }
             if (ring_thread) {
                 const double t1 = Tn + (st + 1) * a.dt;
