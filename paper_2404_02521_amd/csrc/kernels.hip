@@ -421,6 +421,8 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
         __syncthreads();
         T* cur = buf0;
         T* nxt = buf1;
+        const double dq = exp(-a.bc.r * a.dt);
+        double disc = ring_thread ? exp(-a.bc.r * (Tn + first * a.dt)) : 1.0;
         for (int st = first; st < a.steps; ++st) {
             if (nr > 0) {
                 // three-row window in slots 0..2 (row I in slot (I - I0 + 2) % 3 after
@@ -456,8 +458,11 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
                 if (r + 1 < nr) row(r + 1, K1{}, K2{}, K0{});
             }
             if (ring_thread) {
+                // e^{-r t1} carried as a running product (one multiply per step)
+                disc *= dq;
                 const double t1 = Tn + (st + 1) * a.dt;
-                nxt[rI * nc + rJ] = (T)(gring(t1) - (FP32 ? gT : 0.0));
+                nxt[rI * nc + rJ] =
+                    (T)(ring_value<CHEAP>(a.bc, rI * hc, rJ * hc, t1, disc) - (FP32 ? gT : 0.0));
             }
             __syncthreads();
             T* t = cur; cur = nxt; nxt = t;
