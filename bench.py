@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-fno", action="store_true", help="skip the neural coarse propagator leg")
     ap.add_argument("--fno-train-only", action="store_true",
                     help="run only the training part of the neural coarse propagator leg")
+    ap.add_argument("--largest-solve", action="store_true",
+                    help="run only the 2049^2, 256-slice solve (LOD G) against serial F")
     ap.add_argument("--largest-share-only", action="store_true",
                     help="run only the 2049^2 x 32-slice step-kernel leg and print its JSON")
     ap.add_argument("--fno-train-s", type=float, default=30.0,
@@ -119,6 +121,9 @@ def main():
             torch.cuda.synchronize()
             del src, dst
         print(json.dumps(largest_share_leg(pr)), flush=True)
+        return
+    if args.largest_solve:
+        print(json.dumps(largest_solve(pr)), flush=True)
         return
     if args.fno_train_only:
         print(json.dumps(fno_leg(pr, [], [], {}, args.fno_train_s, parareal=False)), flush=True)
@@ -255,6 +260,37 @@ def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
             "p50_ms": round(nearest_rank(lat, 50), 3), "p99_ms": round(nearest_rank(lat, 99), 3),
             "iters": iters, "max_err_vs_serial_f": max(errs),
             "parareal_ms": [round(x, 2) for x in lat]}
+
+
+def largest_solve(pr):
+    """The largest single solve: 2049^2 FP32, N = 256 slices, T = 2 (7207 explicit
+    steps per slice), Parareal with the same-grid implicit G (4 steps per slice)
+    against the GPU's serial F; error in the relative max norm."""
+    import torch
+    from synthetic import largest_single
+    inst = largest_single().replace(coarse_steps_per_slice=4)
+    sv = pr.Solver(inst, coarse_kind=pr.PR_G_LOD, flags=pr.PR_FLAG_TIME_STEPS)
+    t = time.perf_counter()
+    ser = sv.serial_fine()
+    torch.cuda.synchronize()
+    t_ser = time.perf_counter() - t
+    ref = ser.value.clone()
+    t = time.perf_counter()
+    r = sv.solve()
+    torch.cuda.synchronize()
+    t_par = time.perf_counter() - t
+    err = float((r.value - ref).abs().max() / ref.abs().max())
+    st = r.stats
+    out = {"workload": "2049^2 FP32 increment form, N=256, T=2, LOD G (4 steps per slice)",
+           "workspace_gb": round(sv.workspace_bytes / 2 ** 30, 2),
+           "fine_steps_per_slice": st["fine_steps"], "serial_f_s": round(t_ser, 2),
+           "parareal_s": round(t_par, 2), "iters": r.iters, "err_vs_serial_f": err,
+           "increments": [float("%.3g" % x) for x in r.increments],
+           "step_kernel_gbs": round(st["timed_step_bytes"] / (st["t_step_kernels_ms"] * 1e-3) / 1e9, 1),
+           "phase_ms": {"fine": round(st["t_fine_ms"], 1),
+                        "g_and_corrections": round(st["t_chain_ms"] + st["t_correct_ms"], 1)}}
+    sv.close()
+    return out
 
 
 def graph_leg(pr, reps=5):

@@ -153,8 +153,11 @@ typedef struct {
     double increments[PR_MAX_SLICES + 1]; /* increments[k] after iteration k+1 */
     double t_total_ms;          /* wall time of the call, host clock */
     double t_fine_ms;           /* GPU time of the fine sweeps (HIP events) */
-    double t_chain_ms;          /* GPU time of the coarse chains */
-    double t_correct_ms;        /* GPU time of the corrections + norms */
+    double t_chain_ms;          /* GPU time of the coarse chains; with a fine-grid G
+                                   (LOD, FNO, FINE) the chain applies G and the
+                                   correction slice by slice, so this includes the
+                                   corrections and t_correct_ms is 0 */
+    double t_correct_ms;        /* GPU time of the corrections + norms (coarse-grid G) */
     int64_t fine_point_steps;   /* interior node updates performed by F */
     int64_t fine_step_launches; /* explicit-step kernel launches */
     double fine_step_bytes;     /* algorithmic bytes moved by those launches */
