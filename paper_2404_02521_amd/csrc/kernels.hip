@@ -163,8 +163,12 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                                                     const float* __restrict__ lb,
                                                     T* __restrict__ out, StepArgs a) {
     constexpr int W = kWave - 2 * S;
+    static_assert(S < 32, "ring lanes: columns 0 and M-1 use lanes 0..S and 32..32+S");
     const int lane = threadIdx.x & 63;
-    const int wid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6);
+    // the wavefront index is uniform: taken through readfirstlane so that the
+    // row / strip / slice logic below lives in scalar registers and branches
+    const int wid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int strip = wid % a.nstrips;
     const int t = wid / a.nstrips;
     const int chunk = t % a.nchunks;
@@ -179,7 +183,6 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     const int j0 = 1 + strip * W;
     const int jl = j0 - S + lane;
     const bool in_col = (jl >= 1) && (jl <= M - 2);
-    const bool ring_col = (jl == 0) || (jl == M - 1);
     const bool out_lane = (lane >= S) && (lane < S + W) && in_col;
     // no lane of this wavefront sits on or beyond the ring columns
     const bool strip_inner = (j0 - S >= 1) && (j0 - S + kWave - 1 <= M - 2);
@@ -199,6 +202,22 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
         const double x = i * a.bc.h, y = jl * a.bc.h;
         double v = ring_value<CHEAP>(a.bc, x, y, tau[q], disc[q]);
         if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, x, y, Tn, disc_T);
+        return (T)v;
+    };
+    // Ring columns 0 and M-1 inside an interior row: when the newest level-0
+    // row is x, level q needs the ring value at row x - q.  Lane l (l <= S)
+    // evaluates column 0 at level l and lane 32 + l column M-1 at level l, all
+    // in one pass, and the levels pick their value up with readlane; the
+    // values are the same expressions as ring(x - q, q).
+    const bool has_rc = (j0 - S <= 0) || (j0 - S + kWave - 1 >= M - 1);
+    const int rq = min(lane & 31, S);
+    const double rtau = Tn + (a.step + rq) * a.dt;
+    const double rdisc = exp(-a.bc.r * rtau);
+    const double ry = (lane < 32 ? 0 : M - 1) * a.bc.h;
+    auto ring_cols = [&](int x) __attribute__((always_inline)) -> T {
+        const double xx = (x - rq) * a.bc.h;
+        double v = ring_value<CHEAP>(a.bc, xx, ry, rtau, rdisc);
+        if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, xx, ry, Tn, disc_T);
         return (T)v;
     };
 
@@ -228,13 +247,16 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     const int x1 = ib - 1 + S;   // last iteration (level S row ib-1)
     // Prefetch queue: raw loads of rows x..x+PF-1 and Lb rows x-1..x+PF-2 in
     // flight (PF a multiple of 3; row x in slot x % PF).
-    auto raw = [&](int x) -> T {
-        return (x >= 1 && x <= M - 2 && in_col) ? src[(long long)(x - 1) * P + (jl - 1)] : T(0);
-    };
+    // Loads are unconditional, with row and column clamped into the interior,
+    // so no branch surrounds them.  A clamped value is never used as data:
+    // level 0 masks rows and columns outside the interior when it takes the
+    // row in, and Lb only enters rows and lanes whose result is replaced by
+    // ring values or zero, or that feed no output lane.
+    const int jc = min(max(jl, 1), M - 2) - 1;
+    auto raw = [&](int x) -> T { return src[(long long)(min(max(x, 1), M - 2) - 1) * P + jc]; };
     auto rawlb = [&](int rl) -> float {
-        return (MODE == MODE_INCR && rl >= 1 && rl <= M - 2 && in_col)
-                   ? lbs[(long long)(rl - 1) * P + (jl - 1)]
-                   : 0.f;
+        if (MODE != MODE_INCR) return 0.f;
+        return lbs[(long long)(min(max(rl, 1), M - 2) - 1) * P + jc];
     };
     static_assert(PF % 3 == 0, "prefetch depth must be a multiple of the window");
     T pq[PF];
@@ -265,15 +287,18 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
             for (int q = S - 1; q > 0; --q) lbw[q] = lbw[q - 1];
             lbw[0] = cur_lb;
         }
+        T rv = T(0);   // ring-column values of this row's levels (lanes 0..S, 32..32+S)
+        if (!FAST && has_rc) rv = ring_cols(x);
         {
             T c = cur_raw;
             if (!FAST) {
-                c = T(0);
-                if (x <= M - 1) {
-                    if (x == 0 || x == M - 1 || ring_col)
-                        c = (jl >= 0 && jl <= M - 1) ? ring(x, 0) : T(0);
-                    else
-                        c = cur_raw;
+                if (x > M - 1)
+                    c = T(0);
+                else if (x == 0 || x == M - 1)
+                    c = (jl >= 0 && jl <= M - 1) ? ring(x, 0) : T(0);
+                else {
+                    c = in_col ? cur_raw : T(0);
+                    if (has_rc) c = (jl == 0) ? bcast(rv, 0) : ((jl == M - 1) ? bcast(rv, 32) : c);
                 }
             }
             wc[0][K] = c;
@@ -293,8 +318,10 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
             if (!FAST) {
                 if (row < 0 || row > M - 1)
                     c = T(0);
-                else if (row == 0 || row == M - 1 || ring_col)
+                else if (row == 0 || row == M - 1)
                     c = (jl >= 0 && jl <= M - 1) ? ring(row, q) : T(0);
+                else if (has_rc)
+                    c = (jl == 0) ? bcast(rv, q) : ((jl == M - 1) ? bcast(rv, 32 + q) : c);
             }
             if (q == S) {
                 if (row >= ia && row < ib && out_lane) dst[(long long)(row - 1) * P + (jl - 1)] = c;
