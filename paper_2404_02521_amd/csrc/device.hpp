@@ -87,6 +87,18 @@ __device__ inline double bcast(double v, int src) {
     return *reinterpret_cast<double*>(&p);
 }
 
+// Broadcast lane `src` (uniform across the wavefront, not necessarily a
+// compile-time constant) to the whole wavefront.
+__device__ inline float bcast_u(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double bcast_u(double v, int src) {
+    int2 p = *reinterpret_cast<int2*>(&v);
+    p.x = __builtin_amdgcn_readlane(p.x, src);
+    p.y = __builtin_amdgcn_readlane(p.y, src);
+    return *reinterpret_cast<double*>(&p);
+}
+
 // Workgroup-to-XCD-aware remap: the hardware hands consecutive workgroup ids
 // to the 8 XCDs in turn; renumber so each XCD sees a contiguous range of
 // logical tiles (neighbouring tiles share halo rows in that XCD's L2).

@@ -23,6 +23,7 @@
 namespace pr {
 
 enum { MODE_DIRECT = 0, MODE_INCR = 1, MODE_PREP = 2 };
+enum { P_GEN = 0, P_MID = 1, P_FAST = 2 };   // row paths of the temporally blocked kernel
 
 // f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled.
 template <int N, int I = 0, class Fn>
@@ -184,42 +185,48 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     const int jl = j0 - S + lane;
     const bool in_col = (jl >= 1) && (jl <= M - 2);
     const bool out_lane = (lane >= S) && (lane < S + W) && in_col;
-    // no lane of this wavefront sits on or beyond the ring columns
-    const bool strip_inner = (j0 - S >= 1) && (j0 - S + kWave - 1 <= M - 2);
+    // ring columns (0 and M-1) that fall inside this wavefront's 64 columns
+    const bool rc_left = j0 - S <= 0, rc_right = j0 - S + kWave - 1 >= M - 1;
+    const int n_rc = (rc_left ? 1 : 0) + (rc_right ? 1 : 0);
+    const int jring = rc_right ? M - 1 : 0;   // the ring column when n_rc == 1
     const int ia = 1 + chunk * a.rows;
     const int ib = min(ia + a.rows, M - 1);
     const T* src = in + (long long)s * a.g.stride;
     const float* lbs = lb + (long long)s * a.g.stride;
     T* dst = out + (long long)s * a.g.stride;
 
-    double tau[S + 1], disc[S + 1];
-#pragma unroll
-    for (int q = 0; q <= S; ++q) {
-        tau[q] = Tn + (a.step + q) * a.dt;
-        disc[q] = exp(-a.bc.r * tau[q]);
-    }
+    // ring value at node (i, jl), level q; only the ring rows use it, so the
+    // level's time and discount are formed on the spot
     auto ring = [&](int i, int q) __attribute__((always_inline)) -> T {
         const double x = i * a.bc.h, y = jl * a.bc.h;
-        double v = ring_value<CHEAP>(a.bc, x, y, tau[q], disc[q]);
+        const double tq = Tn + (a.step + q) * a.dt;
+        double v = ring_value<CHEAP>(a.bc, x, y, tq, exp(-a.bc.r * tq));
         if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, x, y, Tn, disc_T);
         return (T)v;
     };
-    // Ring columns 0 and M-1 inside an interior row: when the newest level-0
-    // row is x, level q needs the ring value at row x - q.  Lane l (l <= S)
-    // evaluates column 0 at level l and lane 32 + l column M-1 at level l, all
-    // in one pass, and the levels pick their value up with readlane; the
-    // values are the same expressions as ring(x - q, q).
-    const bool has_rc = (j0 - S <= 0) || (j0 - S + kWave - 1 >= M - 1);
-    const int rq = min(lane & 31, S);
-    const double rtau = Tn + (a.step + rq) * a.dt;
-    const double rdisc = exp(-a.bc.r * rtau);
-    const double ry = (lane < 32 ? 0 : M - 1) * a.bc.h;
-    auto ring_cols = [&](int x) __attribute__((always_inline)) -> T {
-        const double xx = (x - rq) * a.bc.h;
-        double v = ring_value<CHEAP>(a.bc, xx, ry, rtau, rdisc);
-        if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, xx, ry, Tn, disc_T);
+    // Ring columns inside interior rows.  When the newest level-0 row is x,
+    // level q needs the ring value at row x - q.  One pass over the lanes
+    // evaluates them for three consecutive newest rows x + k (k = 0..2), both
+    // ring columns c and every level q: lane RS (2k + c) + q holds column c
+    // (0: column 0, 1: column M-1), level q, row x + k - q, and the levels
+    // pick their values up with readlane.  The values are the same
+    // expressions as ring(x + k - q, q).
+    constexpr int RS = S + 1;
+    static_assert(6 * RS <= kWave, "ring lanes: 3 rows x 2 columns x (S + 1) levels");
+    const int bl = min(lane, 6 * RS - 1);
+    const int bq = bl % RS;
+    const int boff = bl / (2 * RS) - bq;   // row offset k - q
+    const bool bcol = (bl / RS) & 1;
+    const double btau = Tn + (a.step + bq) * a.dt;
+    const double bdisc = exp(-a.bc.r * btau);
+    auto ring_batch = [&](int x) __attribute__((always_inline)) -> T {
+        const double xx = (x + boff) * a.bc.h, yy = (bcol ? M - 1 : 0) * a.bc.h;
+        double v = ring_value<CHEAP>(a.bc, xx, yy, btau, bdisc);
+        if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, xx, yy, Tn, disc_T);
         return (T)v;
     };
+    const bool ring_lane = jl == jring;   // P_MID: this lane is the ring column
+    const int rlane = rc_right ? RS : 0;    // P_MID: first ring lane of that column
 
     const T fj = (T)jl;
     const T a1 = (T)a.c.a1, hr = (T)a.c.hr;
@@ -269,13 +276,17 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     }
 
     // One row iteration; the newest window slot is x % 3 = K and the prefetch
-    // slot x % PF = KP (both compile time).
-    // FAST (compile time): every row touched (x-S .. x) is interior and no lane
-    // is on the ring, so no boundary logic is compiled in.
-    auto iter = [&](auto KPc, auto Fc, int x) __attribute__((always_inline)) {
+    // slot x % PF = KP (both compile time).  PATH (compile time):
+    //  P_FAST: every row touched (x-S .. x) is interior and no lane is on the
+    //          ring, so no boundary logic is compiled in;
+    //  P_MID : rows as for P_FAST, one ring column in the wavefront; its values
+    //          for rows x .. x+2 are evaluated when K = 0 (x % 3 == 0);
+    //  P_GEN : anything (ring rows, rows outside the grid, both ring columns).
+    T rvb = T(0);   // ring values of the current three rows (P_MID)
+    auto iter = [&](auto KPc, auto Pc, int x) __attribute__((always_inline)) {
         constexpr int KP = decltype(KPc)::value;
         constexpr int K = KP % 3;
-        constexpr bool FAST = decltype(Fc)::value;
+        constexpr int PATH = decltype(Pc)::value;
         constexpr int K1 = (K + 2) % 3;   // previous row
         constexpr int K2 = (K + 1) % 3;   // row before that
         const T cur_raw = pq[KP];
@@ -287,18 +298,31 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
             for (int q = S - 1; q > 0; --q) lbw[q] = lbw[q - 1];
             lbw[0] = cur_lb;
         }
-        T rv = T(0);   // ring-column values of this row's levels (lanes 0..S, 32..32+S)
-        if (!FAST && has_rc) rv = ring_cols(x);
+        T rv = T(0);   // P_GEN: ring values of this row (lanes with k = 0)
+        if (PATH == P_GEN && n_rc > 0) rv = ring_batch(x);
+        if (PATH == P_MID && K == 0) rvb = ring_batch(x);
+        // value of the wavefront's ring column at level q (P_MID)
+        auto mid_ring = [&](int q) __attribute__((always_inline)) -> T {
+            return bcast_u(rvb, rlane + RS * 2 * K + q);
+        };
         {
             T c = cur_raw;
-            if (!FAST) {
+            // readlane is evaluated by the whole wavefront before the select:
+            // under a lane condition it would become a branch
+            if (PATH == P_MID) {
+                const T rv0 = mid_ring(0);
+                c = ring_lane ? rv0 : c;
+            } else if (PATH == P_GEN) {
                 if (x > M - 1)
                     c = T(0);
                 else if (x == 0 || x == M - 1)
                     c = (jl >= 0 && jl <= M - 1) ? ring(x, 0) : T(0);
                 else {
                     c = in_col ? cur_raw : T(0);
-                    if (has_rc) c = (jl == 0) ? bcast(rv, 0) : ((jl == M - 1) ? bcast(rv, 32) : c);
+                    if (n_rc > 0) {
+                        const T rl = bcast(rv, 0), rr_ = bcast(rv, RS);
+                        c = (jl == 0) ? rl : ((jl == M - 1) ? rr_ : c);
+                    }
                 }
             }
             wc[0][K] = c;
@@ -315,13 +339,18 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
             const T L = A * (up - T(2) * u0 + um) + bj * (r0 - T(2) * u0 + l0) + G * mix +
                         Mu * dd + nj * (r0 - l0) - rr * u0;
             T c = (MODE == MODE_INCR) ? u0 + dt * ((T)lbw[q - 1] + L) : u0 + dt * L;
-            if (!FAST) {
-                if (row < 0 || row > M - 1)
+            if (PATH == P_MID) {
+                const T rvq = mid_ring(q);
+                c = ring_lane ? rvq : c;
+            } else if (PATH == P_GEN) {
+                if (row < 0 || row > M - 1) {
                     c = T(0);
-                else if (row == 0 || row == M - 1)
+                } else if (row == 0 || row == M - 1) {
                     c = (jl >= 0 && jl <= M - 1) ? ring(row, q) : T(0);
-                else if (has_rc)
-                    c = (jl == 0) ? bcast(rv, q) : ((jl == M - 1) ? bcast(rv, 32 + q) : c);
+                } else if (n_rc > 0) {
+                    const T rl = bcast(rv, q), rr_ = bcast(rv, RS + q);
+                    c = (jl == 0) ? rl : ((jl == M - 1) ? rr_ : c);
+                }
             }
             if (q == S) {
                 if (row >= ia && row < ib && out_lane) dst[(long long)(row - 1) * P + (jl - 1)] = c;
@@ -330,20 +359,29 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
             }
         }
     };
-    using F0 = std::integral_constant<bool, false>;
-    using F1 = std::integral_constant<bool, true>;
     auto general = [&](int x) __attribute__((always_inline)) {
         static_for<PF>([&](auto Kc) {
-            if (x % PF == decltype(Kc)::value) iter(Kc, F0{}, x);
+            if (x % PF == decltype(Kc)::value) iter(Kc, std::integral_constant<int, P_GEN>{}, x);
         });
     };
-    // interior iterations: x in [S+1, M-2] for strips away from the ring columns
-    const int fb = strip_inner ? max(x0, S + 1) : x1 + 1;
-    const int fe = strip_inner ? min(x1, M - 2) : x1;
+    // interior iterations: x in [S+1, M-2] for wavefronts with at most one
+    // ring column (P_MID also evaluates rows up to x + 2 <= M - 2)
+    const bool interior = n_rc <= 1;
+    const int fb = interior ? max(x0, S + 1) : x1 + 1;
+    const int fe = interior ? min(x1, M - 2) : x1;
     int x = x0;
     while (x <= x1 && (x < fb || x % PF != 0)) general(x++);
-    for (; x + PF - 1 <= fe; x += PF)
-        static_for<PF>([&](auto Kc) { iter(Kc, F1{}, x + decltype(Kc)::value); });
+    if (n_rc == 0) {
+        for (; x + PF - 1 <= fe; x += PF)
+            static_for<PF>([&](auto Kc) {
+                iter(Kc, std::integral_constant<int, P_FAST>{}, x + decltype(Kc)::value);
+            });
+    } else {
+        for (; x + PF - 1 <= fe; x += PF)
+            static_for<PF>([&](auto Kc) {
+                iter(Kc, std::integral_constant<int, P_MID>{}, x + decltype(Kc)::value);
+            });
+    }
     while (x <= x1) general(x++);
 }
 

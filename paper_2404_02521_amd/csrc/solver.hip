@@ -215,6 +215,8 @@ struct pr_solver {
     int step_ev_used = 0;
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
     int fuse = 6;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
+    int fuse_small = 4;                // ... when a sweep has few slices (PR_STEP_FUSE_SMALL)
+    int small_count = 32;              // "few": at most this many slices (PR_STEP_SMALL_COUNT)
     int wave_target = 6144;            // wavefronts a step launch aims for (PR_STEP_WAVES)
     int min_rows = 8;                  // shortest row chunk of a step launch (PR_STEP_MINROWS)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
@@ -291,6 +293,9 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
                      const float** dres, const double** wres, double* step_ms) {
     const Grid& g = s->fg;
     const long long off = tmp ? 0 : (long long)first * g.stride;
+    // a launch over few slices has too few wavefronts to hide the latency of
+    // its rows; fewer fused steps shorten each wavefront's row walk
+    const int fuse = count <= s->small_count ? s->fuse_small : s->fuse;
     if (s->fp32) {
         float* A = s->at<float>(tmp ? s->L.tA : s->L.dA) + off;
         float* B = s->at<float>(tmp ? s->L.tB : s->L.dB) + off;
@@ -299,7 +304,7 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         HIPCHK(launch_fine_prep(Ubase + (long long)first * g.stride, Lb, A, a, s->stream));
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
         for (int q = 1; q < s->mF;) {
-            const int S = std::min(s->fuse, s->mF - q);
+            const int S = std::min(fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
             const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
                             s->step_ev_used + 2 <= (int)s->step_ev.size();
@@ -326,7 +331,7 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         double* B = s->at<double>(tmp ? s->L.twB : s->L.wB) + off;
         if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
         for (int q = 0; q < s->mF;) {
-            const int S = std::min(s->fuse, s->mF - q);
+            const int S = std::min(fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
             const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
                             s->step_ev_used + 2 <= (int)s->step_ev.size();
@@ -907,6 +912,9 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     s->ring_max_T = host_ring_max(s, model->T);
     if (const char* e = std::getenv("PR_STEP_ROWS")) s->rows_override = std::atoi(e);
     if (const char* e = std::getenv("PR_STEP_FUSE")) s->fuse = std::max(1, std::min(8, std::atoi(e)));
+    if (const char* e = std::getenv("PR_STEP_FUSE_SMALL"))
+        s->fuse_small = std::max(1, std::min(8, std::atoi(e)));
+    if (const char* e = std::getenv("PR_STEP_SMALL_COUNT")) s->small_count = std::atoi(e);
     if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_TIME_EVERY")) s->ev_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_MINROWS")) s->min_rows = std::max(1, std::atoi(e));

@@ -82,6 +82,29 @@ def test_ragged_grids_fp64(pr, M, Mc, N):
     assert abs_max(host(res.value), U) <= FP64_TOL
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("fuse", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_every_fused_step_count(pr, monkeypatch, fuse, fp32):
+    """Every fused-step count S = 1..8 of the temporally blocked step kernel (and
+    the remainder launch: 3 x 23 steps leave 23 mod S) on a ragged grid whose
+    strips of 64 - 2S columns and row chunks end part-way, F over three slices
+    against the oracle's serial F."""
+    monkeypatch.setenv("PR_STEP_FUSE", str(fuse))
+    monkeypatch.setenv("PR_STEP_SMALL_COUNT", "0")
+    monkeypatch.setenv("PR_STEP_MINROWS", "5")
+    inst = plain_fp64(EXCHANGE).replace(M=151, coarse_M=31, n_slices=3, fine_steps_per_slice=23,
+                                        coarse_steps_per_slice=2, T=0.012, fp32=fp32)
+    say("fused step count", fuse, fp32)
+    s = pr.Solver(inst)
+    gpu = host(s.serial_fine().value)
+    ref = oracle.serial_fine(oproblem(inst), 3, inst.T, 23)
+    if fp32:
+        assert rel_max(gpu, ref) <= FP32_TOL
+    else:
+        assert abs_max(gpu, ref) <= FP64_TOL
+    s.close()
+
+
 def test_exact_bc_fp64(pr):
     """Margrabe ring (exchange) through the closed-form ring path."""
     inst = plain_fp64(EXCHANGE)
@@ -216,11 +239,13 @@ def test_full_size_parareal_error_vs_serial(pr):
     assert err <= FP32_TOL, (res.iters, err)
 
 
-def test_max_size_fused_launch_2049(pr):
+def test_max_size_fused_launch_2049(pr, monkeypatch):
     """The largest grid (2049^2) through exactly one prep step plus one 6-step
     fused launch of the FP32 increment kernel, against the FP64 oracle; the
     increment F(u) - u is checked on its own scale."""
     from synthetic import largest_single
+    monkeypatch.setenv("PR_STEP_FUSE", "6")
+    monkeypatch.setenv("PR_STEP_SMALL_COUNT", "0")
     inst = largest_single().replace(n_slices=1, T=7e-6, fine_steps_per_slice=7,
                                     coarse_steps_per_slice=1)
     p = oproblem(inst)
