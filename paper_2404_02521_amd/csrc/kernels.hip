@@ -398,34 +398,37 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
 // c_n) is double-buffered in LDS; c_n and the FP32 Lb = L c_n live in global
 // memory (L2-resident).  Each thread owns one coarse column J and a segment of
 // consecutive rows, walked with a 3-row register window; row coefficients
-// come from an LDS table.
+// come from an LDS table.  NC > 0 compiles the coarse side in (NC = a.nc),
+// so that every neighbour and row offset becomes an immediate.
 // ---------------------------------------------------------------------------
-template <bool CHEAP, bool FP32>
+template <bool CHEAP, bool FP32, int NC>
 __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
     const double* __restrict__ Ucur, const void* __restrict__ Fold, double* __restrict__ Gold,
     double* __restrict__ dcor, double* __restrict__ cst, float* __restrict__ lbc, ChainArgs a) {
     using T = typename std::conditional<FP32, float, double>::type;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
-    const int nc = a.nc, nin = nc - 2, nn = nc * nc;
+    const int nc = NC > 0 ? NC : a.nc, nin = nc - 2, nn = nc * nc;
     const int q = a.q;
     const long long FS = a.fg.stride;
     const int FP = a.fg.pitch;
     const double hc = a.bc.h;
-    // Row weights of the operator in the form
+    // One explicit step u+ = u + dt (Lb + L u) with the operator in the form
     //   L = (A+Mu) u_{I+1} + (A-Mu) u_{I-1} + (B+Nu) u_{J+1} + (B-Nu) u_{J-1}
     //       + G (mixed difference) - (2A + 2B + r) u,
-    // A = a1 I^2, Mu = hr I, B = a2 J^2, Nu = hr J, G = g12 I J: per row
-    // [A+Mu, A-Mu, 2A+r, g12 I] in LDS (read as a broadcast), per column in registers.
+    // A = a1 I^2, Mu = hr I, B = a2 J^2, Nu = hr J, G = g12 I J, and dt folded
+    // into the weights: per row [dt(A+Mu), dt(A-Mu), 1 - dt(2A+r), dt g12 I]
+    // in LDS (read as a broadcast), per column dt(B+Nu), dt(B-Nu), 2 dt B in
+    // registers; the FP32 path keeps dt Lb per node.
     T* tab = reinterpret_cast<T*>(lds);                 // 4*nc row weights
     T* buf0 = tab + 4 * nc;                            // nc*nc
     T* buf1 = buf0 + nn;                               // nc*nc
     for (int I = tid; I < nc; I += kChainThreads) {
         const double A = a.c.a1 * I * I, Mu = a.c.hr * I;
-        tab[4 * I] = (T)(A + Mu);
-        tab[4 * I + 1] = (T)(A - Mu);
-        tab[4 * I + 2] = (T)(2.0 * A + a.c.r);
-        tab[4 * I + 3] = (T)(a.c.g12 * I);
+        tab[4 * I] = (T)(a.dt * (A + Mu));
+        tab[4 * I + 1] = (T)(a.dt * (A - Mu));
+        tab[4 * I + 2] = (T)(1.0 - a.dt * (2.0 * A + a.c.r));
+        tab[4 * I + 3] = (T)(a.dt * a.c.g12 * I);
     }
     // Ring nodes: thread tid < 4*(nc-1) owns ring node number tid.
     const bool ring_thread = tid < 4 * (nc - 1);
@@ -448,8 +451,8 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
     const int I0 = 1 + (tid / ncolt) * rows;
     const int nr = (J <= nin) ? max(0, min(rows, nc - 1 - I0)) : 0;
     const double bJd = a.c.a2 * J * J, nJd = a.c.hr * J;
-    const T cpJ = (T)(bJd + nJd), cmJ = (T)(bJd - nJd), b2J = (T)(2.0 * bJd), fJ = (T)J,
-            dt = (T)a.dt;
+    const T cpJ = (T)(a.dt * (bJd + nJd)), cmJ = (T)(a.dt * (bJd - nJd)),
+            b2J = (T)(a.dt * 2.0 * bJd), fJ = (T)J;
 
     // c_{k0} = R U_{k0}
     for (int r = 0; r < nr; ++r)
@@ -477,7 +480,7 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
                                  a.c.g12 * I * J * (c[nc + 1] + c[-nc - 1] - c[nc - 1] - c[-nc + 1]) +
                                  a.c.hr * I * (c[nc] - c[-nc]) + a.c.hr * J * (c[1] - c[-1]) -
                                  a.c.r * c[0];
-                lbc[I * nc + J] = (float)L;
+                lbc[I * nc + J] = (float)(a.dt * L);
                 buf0[I * nc + J] = (T)(a.dt * L);
             }
             if (ring_thread) buf0[rI * nc + rJ] = (T)(gring(Tn + a.dt) - gT);
@@ -491,11 +494,15 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
         for (int st = first; st < a.steps; ++st) {
             if (nr > 0) {
                 // three-row window in slots 0..2 (row I in slot (I - I0 + 2) % 3 after
-                // it is loaded); the loop is unrolled by 3 so rotating it costs no moves
-                T wl[3], wc[3], wr[3];
+                // it is loaded); the loop is unrolled by 3 so rotating it costs no moves.
+                // dx = u_{J+1} - u_{J-1} of each window row gives the mixed
+                // difference as dx_{I+1} - dx_{I-1}.
+                T wl[3], wc[3], wr[3], dx[3];
                 wl[0] = cur[(I0 - 1) * nc + J - 1]; wc[0] = cur[(I0 - 1) * nc + J];
                 wr[0] = cur[(I0 - 1) * nc + J + 1];
                 wl[1] = cur[I0 * nc + J - 1]; wc[1] = cur[I0 * nc + J]; wr[1] = cur[I0 * nc + J + 1];
+                dx[0] = wr[0] - wl[0];
+                dx[1] = wr[1] - wl[1];
                 auto row = [&](int r, auto Uc, auto Cc, auto Dc) __attribute__((always_inline)) {
                     constexpr int U = decltype(Uc)::value, Cs = decltype(Cc)::value,
                                   D = decltype(Dc)::value;
@@ -503,12 +510,17 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
                     wl[D] = cur[(I + 1) * nc + J - 1];
                     wc[D] = cur[(I + 1) * nc + J];
                     wr[D] = cur[(I + 1) * nc + J + 1];
+                    dx[D] = wr[D] - wl[D];
                     const T* w = tab + 4 * I;
-                    const T wd = w[2] + b2J, G = w[3] * fJ;
+                    const T wd = w[2] - b2J, G = w[3] * fJ;
                     const T c = wc[Cs];
-                    const T L = w[0] * wc[D] + w[1] * wc[U] + cpJ * wr[Cs] + cmJ * wl[Cs] +
-                                G * (wr[D] + wl[U] - wl[D] - wr[U]) - wd * c;
-                    nxt[I * nc + J] = FP32 ? c + dt * ((T)lbc[I * nc + J] + L) : c + dt * L;
+                    T acc = FP32 ? wd * c + (T)lbc[I * nc + J] : wd * c;
+                    acc += w[0] * wc[D];
+                    acc += w[1] * wc[U];
+                    acc += cpJ * wr[Cs];
+                    acc += cmJ * wl[Cs];
+                    acc += G * (dx[D] - dx[U]);
+                    nxt[I * nc + J] = acc;
                 };
                 using K0 = std::integral_constant<int, 0>;
                 using K1 = std::integral_constant<int, 1>;
@@ -777,9 +789,16 @@ hipError_t launch_fine_prep(const double* base, float* lb, float* d1, const Step
     return launch_step<MODE_PREP, double, float>(base, nullptr, lb, d1, a, st);
 }
 
+// the coarse side compiled into the chain kernel (the at-scale coarse grid)
+constexpr int kChainNC = 129;
+
 hipError_t chain_set_lds(int bytes) {
-    const void* fns[4] = {(const void*)k_coarse_chain<true, true>, (const void*)k_coarse_chain<true, false>,
-                          (const void*)k_coarse_chain<false, true>, (const void*)k_coarse_chain<false, false>};
+    const void* fns[6] = {(const void*)k_coarse_chain<true, true, 0>,
+                          (const void*)k_coarse_chain<true, false, 0>,
+                          (const void*)k_coarse_chain<false, true, 0>,
+                          (const void*)k_coarse_chain<false, false, 0>,
+                          (const void*)k_coarse_chain<true, true, kChainNC>,
+                          (const void*)k_coarse_chain<true, false, kChainNC>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -795,13 +814,15 @@ int chain_lds_bytes(int nc, int fp32) {
 hipError_t launch_chain(const double* Ucur, const void* Fold, double* Gold, double* dcor,
                         double* cst, float* lbc, const ChainArgs& a, hipStream_t st) {
     const int lds = chain_lds_bytes(a.nc, a.fp32);
-#define PR_CHAIN(C, F)                                                                    \
-    hipLaunchKernelGGL((k_coarse_chain<C, F>), dim3(1), dim3(kChainThreads), lds, st, Ucur, Fold, \
-                       Gold, dcor, cst, lbc, a)
+#define PR_CHAIN(C, F, N)                                                                   \
+    hipLaunchKernelGGL((k_coarse_chain<C, F, N>), dim3(1), dim3(kChainThreads), lds, st, Ucur,   \
+                       Fold, Gold, dcor, cst, lbc, a)
     if (a.bc.kind == 2) {
-        if (a.fp32) PR_CHAIN(false, true); else PR_CHAIN(false, false);
+        if (a.fp32) PR_CHAIN(false, true, 0); else PR_CHAIN(false, false, 0);
+    } else if (a.nc == kChainNC) {
+        if (a.fp32) PR_CHAIN(true, true, kChainNC); else PR_CHAIN(true, false, kChainNC);
     } else {
-        if (a.fp32) PR_CHAIN(true, true); else PR_CHAIN(true, false);
+        if (a.fp32) PR_CHAIN(true, true, 0); else PR_CHAIN(true, false, 0);
     }
 #undef PR_CHAIN
     return hipGetLastError();
