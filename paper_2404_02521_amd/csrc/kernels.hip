@@ -455,6 +455,7 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
             b2J = (T)(a.dt * 2.0 * bJd), fJ = (T)J;
 
     // c_{k0} = R U_{k0}
+#pragma unroll 4
     for (int r = 0; r < nr; ++r)
         cst[(I0 + r) * nc + J] =
             Ucur[(long long)a.k0 * FS + (long long)((I0 + r) * q - 1) * FP + (J * q - 1)];
@@ -472,6 +473,7 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
             // increment dt*Lb, ring increment 0 at T_n.
             if (ring_thread) cst[rI * nc + rJ] = gT;
             __syncthreads();
+#pragma unroll 2
             for (int r = 0; r < nr; ++r) {
                 const int I = I0 + r;
                 const double* c = cst + I * nc + J;
@@ -551,21 +553,48 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
             Go[rI * nc + rJ] = gring(Tn + a.steps * a.dt);
             dc[rI * nc + rJ] = 0.0;
         }
-        for (int r = 0; r < nr; ++r) {
-            const int I = I0 + r, off = I * nc + J;
-            const double g = FP32 ? cst[off] + (double)cur[off] : (double)cur[off];
-            if (a.init) {
-                Go[off] = g;
-                dc[off] = 0.0;
-                cst[off] = g;
-            } else {
-                const double d = g - Go[off];
-                Go[off] = g;
-                dc[off] = d;
+        // Rows are taken EB at a time, every load of a batch issued before the
+        // first use (rows clamped into the segment), so that a batch waits for
+        // memory once instead of once per row.
+        constexpr int EB = 4;
+        for (int r0 = 0; r0 < nr; r0 += EB) {
+            double cs[EB], go[EB], fu[EB];
+            float ff[EB];
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int I = I0 + min(r0 + e, nr - 1), off = I * nc + J;
                 const long long fo = (long long)n * FS + (long long)(I * q - 1) * FP + (J * q - 1);
-                const double fold = FP32 ? Ucur[fo] + (double)((const float*)Fold)[fo]
-                                         : ((const double*)Fold)[fo];
-                cst[off] = fold + d;
+                cs[e] = FP32 ? cst[off] : 0.0;
+                go[e] = 0.0;
+                fu[e] = 0.0;
+                ff[e] = 0.f;
+                if (!a.init) {
+                    go[e] = Go[off];
+                    if (FP32) {
+                        fu[e] = Ucur[fo];
+                        ff[e] = ((const float*)Fold)[fo];
+                    } else {
+                        fu[e] = ((const double*)Fold)[fo];
+                    }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                if (r0 + e < nr) {
+                    const int off = (I0 + r0 + e) * nc + J;
+                    const double g = FP32 ? cs[e] + (double)cur[off] : (double)cur[off];
+                    if (a.init) {
+                        Go[off] = g;
+                        dc[off] = 0.0;
+                        cst[off] = g;
+                    } else {
+                        const double d = g - go[e];
+                        Go[off] = g;
+                        dc[off] = d;
+                        const double fold = FP32 ? fu[e] + (double)ff[e] : fu[e];
+                        cst[off] = fold + d;
+                    }
+                }
             }
         }
         __syncthreads();
