@@ -13,7 +13,8 @@ outside the timed region.
 
 Prints ONE JSON line: solves/s (value), per-solve latency p50/p99, the
 roofline of the dominant kernel (the FP32 explicit step) from HIP events
-around every step launch, and the FP64 oracle timed on the host cores.
+around every 8th step launch of each sweep, and the FP64 oracle timed on the
+host cores.
 """
 from __future__ import annotations
 
@@ -35,9 +36,13 @@ SEEDS = list(range(8))
 
 
 def kernel_source_hash() -> str:
+    """First 16 hex digits of sha256 over the step kernel's source and the
+    solver that sets its launch geometry (kernels.hip, then solver.hip)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2404_02521_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "solver.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2404_02521_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic_per_point_step(name="k_fine_tb_513x513x64_fp32.md"):

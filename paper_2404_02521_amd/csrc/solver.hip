@@ -216,7 +216,8 @@ struct pr_solver {
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
     int fuse = 6;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
     int fuse_small = 4;                // ... when a sweep has few slices (PR_STEP_FUSE_SMALL)
-    int small_count = 32;              // "few": at most this many slices (PR_STEP_SMALL_COUNT)
+    int small_count = 0;               // "few": at most this many slices (PR_STEP_SMALL_COUNT;
+                                       // 0: every sweep uses `fuse`)
     int wave_target = 6144;            // wavefronts a step launch aims for (PR_STEP_WAVES)
     int min_rows = 8;                  // shortest row chunk of a step launch (PR_STEP_MINROWS)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
@@ -293,8 +294,9 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
                      const float** dres, const double** wres, double* step_ms) {
     const Grid& g = s->fg;
     const long long off = tmp ? 0 : (long long)first * g.stride;
-    // a launch over few slices has too few wavefronts to hide the latency of
-    // its rows; fewer fused steps shorten each wavefront's row walk
+    // optional: another fused-step count for sweeps over few slices (their
+    // launches have few wavefronts; off by default, where it measured within
+    // 1% of one count for every sweep)
     const int fuse = count <= s->small_count ? s->fuse_small : s->fuse;
     if (s->fp32) {
         float* A = s->at<float>(tmp ? s->L.tA : s->L.dA) + off;
