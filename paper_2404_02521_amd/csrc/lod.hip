@@ -36,36 +36,45 @@ struct LodArgs {
     int npad;      // power of two >= nin
 };
 
-// Parallel cyclic reduction of a_k x_{k-1} + b_k x_k + c_k x_{k+1} = d_k on
-// k < npad (rows >= n are identity rows; a_0 = c_{n-1} = 0 after folding the
-// end values into d).  Arrays in LDS; returns x_k = d_k / b_k for the caller's
-// own rows.  Every thread takes the same number of barriers.
-__device__ inline void pcr_solve(double* a, double* b, double* c, double* d, int npad) {
+// Parallel cyclic reduction of a_k x_{k-1} + x_k + c_k x_{k+1} = d_k on
+// k < npad, every row normalised to a unit diagonal (rows >= n are identity
+// rows; a_0 = c_{n-1} = 0 after folding the end values into d).  A reduction
+// step with stride s eliminates x_{k-s} and x_{k+s} from row k with rows
+// k - s and k + s and divides the result by its new diagonal, so that each
+// row costs one division per step.  The arrays ping-pong between the two LDS
+// sets (one barrier per step); returns the set that holds x_k = d_k.
+// Every thread takes the same number of barriers.
+struct PcrSet {
+    double* a;
+    double* c;
+    double* d;
+};
+__device__ inline PcrSet pcr_solve(PcrSet in, PcrSet out, int npad) {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    double na[kPcrMaxPerThread], nb[kPcrMaxPerThread], nc[kPcrMaxPerThread], nd[kPcrMaxPerThread];
     for (int s = 1; s < npad; s <<= 1) {
 #pragma unroll
         for (int e = 0; e < kPcrMaxPerThread; ++e) {
             const int k = tid + e * nt;
             if (k < npad) {
                 const int km = k - s, kp = k + s;
-                const double al = km >= 0 ? -a[k] / b[km] : 0.0;
-                const double ga = kp < npad ? -c[k] / b[kp] : 0.0;
-                na[e] = km >= 0 ? al * a[km] : 0.0;
-                nc[e] = kp < npad ? ga * c[kp] : 0.0;
-                nb[e] = b[k] + (km >= 0 ? al * c[km] : 0.0) + (kp < npad ? ga * a[kp] : 0.0);
-                nd[e] = d[k] + (km >= 0 ? al * d[km] : 0.0) + (kp < npad ? ga * d[kp] : 0.0);
+                const double ak = in.a[k], ck = in.c[k];
+                const double am = km >= 0 ? in.a[km] : 0.0, cm = km >= 0 ? in.c[km] : 0.0;
+                const double dm = km >= 0 ? in.d[km] : 0.0;
+                const double ap = kp < npad ? in.a[kp] : 0.0, cp = kp < npad ? in.c[kp] : 0.0;
+                const double dp = kp < npad ? in.d[kp] : 0.0;
+                const double inv = 1.0 / (1.0 - ak * cm - ck * ap);
+                out.a[k] = -ak * am * inv;
+                out.c[k] = -ck * cp * inv;
+                out.d[k] = (in.d[k] - ak * dm - ck * dp) * inv;
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int e = 0; e < kPcrMaxPerThread; ++e) {
-            const int k = tid + e * nt;
-            if (k < npad) { a[k] = na[e]; b[k] = nb[e]; c[k] = nc[e]; d[k] = nd[e]; }
-        }
-        __syncthreads();
+        const PcrSet t = in;
+        in = out;
+        out = t;
     }
+    return in;
 }
 
 // (I - dt Lx) w = u + dt Lxy u along interior column j = blockIdx.x + 1.
@@ -75,10 +84,7 @@ __global__ __launch_bounds__(kPcrThreads) void k_lod_x(const double* __restrict_
                                                        double* __restrict__ w, LodArgs a) {
     extern __shared__ double sm[];
     const int npad = a.npad;
-    double* A = sm;
-    double* B = sm + npad;
-    double* Cc = sm + 2 * npad;
-    double* D = sm + 3 * npad;
+    const PcrSet s0{sm, sm + npad, sm + 2 * npad}, s1{sm + 3 * npad, sm + 4 * npad, sm + 5 * npad};
     const int M = a.g.n, n = a.g.nin, P = a.g.pitch;
     const int j = blockIdx.x + 1;
     const double h = a.bc.h, dt = a.dt;
@@ -105,15 +111,15 @@ __global__ __launch_bounds__(kPcrThreads) void k_lod_x(const double* __restrict_
                                           u_at(i + 1, j - 1) - u_at(i - 1, j + 1));
             if (k == 0) { dk -= ak * endrow(0); ak = 0.0; }
             if (k == n - 1) { dk -= ck * endrow(M - 1); ck = 0.0; }
-            A[k] = ak; B[k] = 1.0 + dt * (2.0 * al + 0.5 * a.c.r); Cc[k] = ck; D[k] = dk;
+            const double ib = 1.0 / (1.0 + dt * (2.0 * al + 0.5 * a.c.r));
+            s0.a[k] = ak * ib; s0.c[k] = ck * ib; s0.d[k] = dk * ib;
         } else {
-            A[k] = 0.0; B[k] = 1.0; Cc[k] = 0.0; D[k] = 0.0;
+            s0.a[k] = 0.0; s0.c[k] = 0.0; s0.d[k] = 0.0;
         }
     }
     __syncthreads();
-    pcr_solve(A, B, Cc, D, npad);
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        w[(long long)k * P + (j - 1)] = D[k] / B[k];
+    const PcrSet x = pcr_solve(s0, s1, npad);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) w[(long long)k * P + (j - 1)] = x.d[k];
 }
 
 // (I - dt Ly) u+ = w along interior row i = blockIdx.x + 1; ends g(i, 0, tau1)
@@ -123,10 +129,7 @@ __global__ __launch_bounds__(kPcrThreads) void k_lod_y(const double* __restrict_
                                                        double* __restrict__ out, LodArgs a) {
     extern __shared__ double sm[];
     const int npad = a.npad;
-    double* A = sm;
-    double* B = sm + npad;
-    double* Cc = sm + 2 * npad;
-    double* D = sm + 3 * npad;
+    const PcrSet s0{sm, sm + npad, sm + 2 * npad}, s1{sm + 3 * npad, sm + 4 * npad, sm + 5 * npad};
     const int M = a.g.n, n = a.g.nin, P = a.g.pitch;
     const int i = blockIdx.x + 1;
     const double h = a.bc.h, dt = a.dt;
@@ -146,15 +149,16 @@ __global__ __launch_bounds__(kPcrThreads) void k_lod_y(const double* __restrict_
                 dk -= ck * ring_value<CHEAP>(a.bc, i * h, (M - 1) * h, a.tau1, disc1);
                 ck = 0.0;
             }
-            A[k] = ak; B[k] = 1.0 + dt * (2.0 * be + 0.5 * a.c.r); Cc[k] = ck; D[k] = dk;
+            const double ib = 1.0 / (1.0 + dt * (2.0 * be + 0.5 * a.c.r));
+            s0.a[k] = ak * ib; s0.c[k] = ck * ib; s0.d[k] = dk * ib;
         } else {
-            A[k] = 0.0; B[k] = 1.0; Cc[k] = 0.0; D[k] = 0.0;
+            s0.a[k] = 0.0; s0.c[k] = 0.0; s0.d[k] = 0.0;
         }
     }
     __syncthreads();
-    pcr_solve(A, B, Cc, D, npad);
+    const PcrSet x = pcr_solve(s0, s1, npad);
     double* orow = out + (long long)(i - 1) * P;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) orow[k] = D[k] / B[k];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) orow[k] = x.d[k];
 }
 
 int lod_npad(int nin) {
@@ -163,8 +167,11 @@ int lod_npad(int nin) {
     return p;
 }
 
+// two sets of three npad-long FP64 arrays (a, c, d)
+int lod_lds_bytes(int nin) { return 6 * lod_npad(nin) * (int)sizeof(double); }
+
 hipError_t lod_set_lds(int nin) {
-    const int bytes = 4 * lod_npad(nin) * (int)sizeof(double);
+    const int bytes = lod_lds_bytes(nin);
     const void* fns[4] = {(const void*)k_lod_x<true>, (const void*)k_lod_x<false>,
                           (const void*)k_lod_y<true>, (const void*)k_lod_y<false>};
     for (const void* f : fns) {
@@ -182,7 +189,7 @@ hipError_t launch_lod_slice(const double* in, double* out, double* work0, double
                             double tau0, int m, hipStream_t st) {
     const int npad = lod_npad(g.nin);
     const int threads = npad < kPcrThreads ? npad : kPcrThreads;
-    const int lds = 4 * npad * (int)sizeof(double);
+    const int lds = lod_lds_bytes(g.nin);
     const double* cur = in;
     for (int q = 0; q < m; ++q) {
         LodArgs a{g, c, bc, dt, tau0 + q * dt, tau0 + (q + 1) * dt, npad};
