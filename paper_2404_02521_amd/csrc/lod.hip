@@ -25,6 +25,8 @@ namespace pr {
 
 constexpr int kPcrThreads = 1024;
 constexpr int kPcrMaxPerThread = 2;   // lines up to 2048 unknowns
+constexpr int kPcrTail = 8;           // unknowns per system left to elimination
+constexpr int kPcrStop = 64;          // stop reduction only when >= 64 systems remain
 
 struct LodArgs {
     Grid g;
@@ -42,7 +44,10 @@ struct LodArgs {
 // step with stride s eliminates x_{k-s} and x_{k+s} from row k with rows
 // k - s and k + s and divides the result by its new diagonal, so that each
 // row costs one division per step.  The arrays ping-pong between the two LDS
-// sets (one barrier per step); returns the set that holds x_k = d_k.
+// sets (one barrier per step).  The reduction stops at stride kPcrStop: the
+// rows then form kPcrStop independent systems k0, k0 + kPcrStop, ... of
+// npad / kPcrStop unknowns each, which threads k0 < kPcrStop solve by
+// elimination and back substitution.  Returns the set that holds x_k = d_k.
 // Every thread takes the same number of barriers.
 struct PcrSet {
     double* a;
@@ -52,7 +57,8 @@ struct PcrSet {
 __device__ inline PcrSet pcr_solve(PcrSet in, PcrSet out, int npad) {
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    for (int s = 1; s < npad; s <<= 1) {
+    const int stop = npad >= kPcrStop * kPcrTail ? npad / kPcrTail : npad;
+    for (int s = 1; s < stop; s <<= 1) {
 #pragma unroll
         for (int e = 0; e < kPcrMaxPerThread; ++e) {
             const int k = tid + e * nt;
@@ -74,6 +80,33 @@ __device__ inline PcrSet pcr_solve(PcrSet in, PcrSet out, int npad) {
         in = out;
         out = t;
     }
+    if (stop < npad && tid < stop) {
+        // rows tid + q * stop, q = 0 .. m-1: a couples to q - 1, c to q + 1
+        const int m = npad / stop;
+        double cprime[kPcrTail], dprime[kPcrTail];
+        double cp = 0.0, dp = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPcrTail; ++q) {
+            const int k = tid + q * stop;
+            if (q < m) {
+                const double ak = in.a[k];
+                const double inv = 1.0 / (1.0 - ak * cp);
+                cp = in.c[k] * inv;
+                dp = (in.d[k] - ak * dp) * inv;
+                cprime[q] = cp;
+                dprime[q] = dp;
+            }
+        }
+        double x = 0.0;
+#pragma unroll
+        for (int q = kPcrTail - 1; q >= 0; --q) {
+            if (q < m) {
+                x = dprime[q] - cprime[q] * x;
+                in.d[tid + q * stop] = x;
+            }
+        }
+    }
+    __syncthreads();
     return in;
 }
 
