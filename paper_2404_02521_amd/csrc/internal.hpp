@@ -15,7 +15,7 @@ namespace pr {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 wavefronts per workgroup
 constexpr int kChainThreads = 1024;  // one workgroup runs the whole coarse chain
-constexpr int kChainMaxPts = 16;     // interior points per chain thread => coarse n <= 129
+constexpr int kChainMaxN = 257;      // coarse nodes per side: 4 (n - 1) ring nodes <= 1024 threads
 
 // Dirichlet data and payoff; everything in index form needs only h.
 struct Bc {
@@ -68,6 +68,8 @@ struct ChainArgs {
     Coef c;
     Bc bc;            // coarse h
     double dt, dT;
+    void* gstate;     // 2 nc^2 elements in global memory holding the stepped coarse
+                      // state when it does not fit in LDS; nullptr: LDS
 };
 
 }  // namespace pr

@@ -399,9 +399,12 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
 // memory (L2-resident).  Each thread owns one coarse column J and a segment of
 // consecutive rows, walked with a 3-row register window; row coefficients
 // come from an LDS table.  NC > 0 compiles the coarse side in (NC = a.nc),
-// so that every neighbour and row offset becomes an immediate.
+// so that every neighbour and row offset becomes an immediate.  GB: the two
+// state buffers live in global memory (a.gstate, L2-resident) for coarse grids
+// whose state does not fit in LDS; the waves of the one workgroup share the
+// CU's L1, so the per-step barrier orders them as it does LDS.
 // ---------------------------------------------------------------------------
-template <bool CHEAP, bool FP32, int NC>
+template <bool CHEAP, bool FP32, int NC, bool GB>
 __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
     const double* __restrict__ Ucur, const void* __restrict__ Fold, double* __restrict__ Gold,
     double* __restrict__ dcor, double* __restrict__ cst, float* __restrict__ lbc, ChainArgs a) {
@@ -421,8 +424,8 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
     // in LDS (read as a broadcast), per column dt(B+Nu), dt(B-Nu), 2 dt B in
     // registers; the FP32 path keeps dt Lb per node.
     T* tab = reinterpret_cast<T*>(lds);                 // 4*nc row weights
-    T* buf0 = tab + 4 * nc;                            // nc*nc
-    T* buf1 = buf0 + nn;                               // nc*nc
+    T* buf0 = GB ? reinterpret_cast<T*>(a.gstate) : tab + 4 * nc;   // nc*nc
+    T* buf1 = buf0 + nn;                                            // nc*nc
     for (int I = tid; I < nc; I += kChainThreads) {
         const double A = a.c.a1 * I * I, Mu = a.c.hr * I;
         tab[4 * I] = (T)(a.dt * (A + Mu));
@@ -820,14 +823,20 @@ hipError_t launch_fine_prep(const double* base, float* lb, float* d1, const Step
 
 // the coarse side compiled into the chain kernel (the at-scale coarse grid)
 constexpr int kChainNC = 129;
+// dynamic LDS one workgroup may take on gfx950
+constexpr int kChainLdsMax = 160 * 1024;
 
 hipError_t chain_set_lds(int bytes) {
-    const void* fns[6] = {(const void*)k_coarse_chain<true, true, 0>,
-                          (const void*)k_coarse_chain<true, false, 0>,
-                          (const void*)k_coarse_chain<false, true, 0>,
-                          (const void*)k_coarse_chain<false, false, 0>,
-                          (const void*)k_coarse_chain<true, true, kChainNC>,
-                          (const void*)k_coarse_chain<true, false, kChainNC>};
+    const void* fns[10] = {(const void*)k_coarse_chain<true, true, 0, false>,
+                           (const void*)k_coarse_chain<true, false, 0, false>,
+                           (const void*)k_coarse_chain<false, true, 0, false>,
+                           (const void*)k_coarse_chain<false, false, 0, false>,
+                           (const void*)k_coarse_chain<true, true, kChainNC, false>,
+                           (const void*)k_coarse_chain<true, false, kChainNC, false>,
+                           (const void*)k_coarse_chain<true, true, 0, true>,
+                           (const void*)k_coarse_chain<true, false, 0, true>,
+                           (const void*)k_coarse_chain<false, true, 0, true>,
+                           (const void*)k_coarse_chain<false, false, 0, true>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -835,23 +844,35 @@ hipError_t chain_set_lds(int bytes) {
     return hipSuccess;
 }
 
+// LDS of the chain kernel: the row table, and the two state buffers when they fit
 int chain_lds_bytes(int nc, int fp32) {
     const int es = fp32 ? 4 : 8;
-    return (4 * nc + 2 * nc * nc) * es;
+    const int all = (4 * nc + 2 * nc * nc) * es;
+    return all <= kChainLdsMax ? all : 4 * nc * es;
+}
+
+bool chain_state_in_lds(int nc, int fp32) {
+    return (4 * nc + 2 * nc * nc) * (fp32 ? 4 : 8) <= kChainLdsMax;
 }
 
 hipError_t launch_chain(const double* Ucur, const void* Fold, double* Gold, double* dcor,
                         double* cst, float* lbc, const ChainArgs& a, hipStream_t st) {
     const int lds = chain_lds_bytes(a.nc, a.fp32);
-#define PR_CHAIN(C, F, N)                                                                   \
-    hipLaunchKernelGGL((k_coarse_chain<C, F, N>), dim3(1), dim3(kChainThreads), lds, st, Ucur,   \
+#define PR_CHAIN(C, F, N, G)                                                                \
+    hipLaunchKernelGGL((k_coarse_chain<C, F, N, G>), dim3(1), dim3(kChainThreads), lds, st, Ucur, \
                        Fold, Gold, dcor, cst, lbc, a)
-    if (a.bc.kind == 2) {
-        if (a.fp32) PR_CHAIN(false, true, 0); else PR_CHAIN(false, false, 0);
+    if (a.gstate) {
+        if (a.bc.kind == 2) {
+            if (a.fp32) PR_CHAIN(false, true, 0, true); else PR_CHAIN(false, false, 0, true);
+        } else {
+            if (a.fp32) PR_CHAIN(true, true, 0, true); else PR_CHAIN(true, false, 0, true);
+        }
+    } else if (a.bc.kind == 2) {
+        if (a.fp32) PR_CHAIN(false, true, 0, false); else PR_CHAIN(false, false, 0, false);
     } else if (a.nc == kChainNC) {
-        if (a.fp32) PR_CHAIN(true, true, kChainNC); else PR_CHAIN(true, false, kChainNC);
+        if (a.fp32) PR_CHAIN(true, true, kChainNC, false); else PR_CHAIN(true, false, kChainNC, false);
     } else {
-        if (a.fp32) PR_CHAIN(true, true, 0); else PR_CHAIN(true, false, 0);
+        if (a.fp32) PR_CHAIN(true, true, 0, false); else PR_CHAIN(true, false, 0, false);
     }
 #undef PR_CHAIN
     return hipGetLastError();

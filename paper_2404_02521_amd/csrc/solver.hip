@@ -32,6 +32,7 @@ hipError_t chain_set_lds(int);
 hipError_t launch_chain(const double*, const void*, double*, double*, double*, float*,
                         const ChainArgs&, hipStream_t);
 int chain_lds_bytes(int, int);
+bool chain_state_in_lds(int, int);
 hipError_t launch_correct(const double*, const void*, const double*, const double*, double*,
                           double*, unsigned long long*, const Grid&, int, int, int, int, int,
                           int, int, hipStream_t);
@@ -102,7 +103,7 @@ double gershgorin_dt(int n, const pr_model& m) {
 struct Layout {
     uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
         lw0, lw1, lwb, Sr, Sp, fwf, fT, fwc, fwc1, fTp, fin, fmeta, fout, fvc0, fvc1, flw0, flw1,
-        flwb, fwb, total;
+        flwb, fwb, gst, total;
 };
 
 bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
@@ -121,9 +122,7 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
         if (o->coarse_n < 3) return fail("coarse_n must be >= 3");
         if ((g->n - 1) % (o->coarse_n - 1) != 0)
             return fail("(n-1) must be divisible by (coarse_n-1)");
-        if (o->coarse_n > 129) return fail("coarse_n above 129 is not supported");
-        if (o->precision == PR_FP64 && o->coarse_n > 89)
-            return fail("coarse_n above 89 is not supported in FP64");
+        if (o->coarse_n > kChainMaxN) return fail("coarse_n above 257 is not supported");
     }
     if (o->coarse_kind == PR_G_LOD && g->n - 2 > 2048)
         return fail("PR_G_LOD supports up to 2050 nodes per side");
@@ -159,6 +158,9 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.dcor = take(N * nc * nc * 8);
     L.cst = take(nc * nc * 8);
     L.lbc = take(nc * nc * 4);
+    // chain state in global memory when it does not fit in LDS
+    L.gst = take(nc > 0 && !chain_state_in_lds((int)nc, fp32 ? 1 : 0) ? 2 * nc * nc * (fp32 ? 4 : 8)
+                                                                       : 0);
     L.Gf = take(fineg ? N * sd : 0);
     L.tA = take(gfine && fp32 ? sf : 0);
     L.tB = take(gfine && fp32 ? sf : 0);
@@ -384,6 +386,7 @@ ChainArgs chain_args(pr_solver* s, int k0, int k1, int init) {
     a.bc = s->bcc;
     a.dt = s->dtG;
     a.dT = s->dT;
+    a.gstate = chain_state_in_lds(s->nc, a.fp32) ? nullptr : (void*)s->at<char>(s->L.gst);
     return a;
 }
 

@@ -76,9 +76,9 @@ def test_plan_fixed_counts_c1():
     inst = plain_fp64()
     mf, mg, _, _ = plan(inst)
     assert (mf, mg) == (128, 64)
-    big = largest_single().replace(coarse_M=129)   # the LDS coarse chain holds up to 129^2
+    big = largest_single()                          # 2049^2 fine, 257^2 coarse
     mf, mg, _, _ = plan(big)
-    assert mf > 7000 and mg > 20
+    assert mf == 7207 and mg > 100
 
 
 def _create(inst, nbytes=1 << 20, ptr=256, **kw):
@@ -96,6 +96,9 @@ def test_validation_before_any_gpu_call():
     assert _create(inst.replace(rho=1.0)) == L.PR_EINVAL
     assert _create(inst.replace(T=0.0)) == L.PR_EINVAL
     assert _create(inst.replace(coarse_M=30)) == L.PR_EINVAL          # 64 % 29 != 0
+    assert _create(inst.replace(M=1025, coarse_M=513)) == L.PR_EINVAL   # coarse above 257
+    g1, _, _, o1 = make_structs(inst.replace(M=1025, coarse_M=257))
+    assert L.lib().parareal_workspace_bytes(C.byref(g1), C.byref(o1)) > 0
     assert _create(inst.replace(fine_steps_per_slice=8)) == L.PR_EUNSTABLE
     assert _create(inst.replace(coarse_steps_per_slice=2)) == L.PR_EUNSTABLE
     assert _create(inst, nbytes=16) == L.PR_ENOMEM
@@ -119,7 +122,7 @@ def test_workspace_size_formula():
     assert nbytes >= 2 * 65 * per * 8 + 3 * 64 * per * 4
     assert nbytes < 1.01 * (2 * 65 * per * 8 + 3 * 64 * per * 4) + 64 * 129 * 129 * 16 + 4096
     big = largest_single()
-    g, _, _, o = make_structs(big.replace(coarse_M=129))
+    g, _, _, o = make_structs(big)
     assert L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o)) < 40e9
 
 

@@ -211,6 +211,29 @@ def test_fp32_parareal_vs_oracle(pr, seed):
         assert np.allclose(res.increments, inc, rtol=1e-3)
 
 
+@pytest.mark.parametrize("fp32,M,Mc", [(True, 513, 257), (False, 257, 129)])
+def test_coarse_chain_state_in_global_memory(pr, fp32, M, Mc):
+    """Coarse grids whose stepped state does not fit in LDS (FP32 257^2, FP64
+    129^2) run the chain with its two state buffers in global memory: Parareal
+    iterates k = 1, 2 against the oracle."""
+    inst = plain_at_scale(3, M=M, n_slices=4, coarse_M=Mc).replace(T=0.04, tol=0.0, fp32=fp32)
+    mf, mg, _, _ = pr.plan(inst)
+    say("chain state in global memory", fp32, M, Mc, mf, mg)
+    for k in (1, 2):
+        s = pr.Solver(inst, max_iters=k)
+        res = s.solve()
+        U, K, inc = oracle.parareal_bs(oproblem(inst), oproblem(inst, Mc), 4, inst.T, mf, mg,
+                                       max_iters=k, tol=0.0)
+        assert res.iters == K == k
+        if fp32:
+            assert rel_max(host(res.value), U) <= FP32_TOL
+            assert np.allclose(res.increments, inc, rtol=1e-3)
+        else:
+            assert abs_max(host(res.value), U) <= FP64_TOL
+            assert np.allclose(res.increments, inc, rtol=1e-8, atol=1e-14)
+        s.close()
+
+
 def test_full_size_fine_slice_vs_oracle(pr):
     """513^2 at the at-scale launch shape: F over slice 0 (planned steps) and G over
     slice 0 (129^2 coarse grid), checked against the oracle."""
