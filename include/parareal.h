@@ -136,7 +136,8 @@ typedef struct {
     int32_t precision;      /* PR_FP64 or PR_FP32 */
     int32_t fine_steps;     /* explicit steps per slice; 0 => planned from cfl */
     int32_t coarse_kind;    /* PR_G_* */
-    int32_t coarse_n;       /* PR_G_NUMERICAL: coarse nodes per side; (n-1) % (coarse_n-1) == 0 */
+    int32_t coarse_n;       /* PR_G_NUMERICAL: coarse nodes per side, 3..257;
+                               (n-1) % (coarse_n-1) == 0 */
     int32_t coarse_steps;   /* coarse steps per slice; 0 => planned from cfl (PR_G_LOD: 2) */
     double cfl;             /* planned dt = dT / ceil(dT / (cfl * dt_stable)); (0, 1] */
     uint32_t flags;         /* PR_FLAG_* bits */
