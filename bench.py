@@ -270,8 +270,9 @@ def lod_leg(pr, insts, seeds, serial_ref, coarse_steps=4):
 def largest_solve(pr):
     """The largest single solve: 2049^2 FP32, N = 256 slices, T = 2 (7207 explicit
     steps per slice), Parareal with the same-grid implicit G (4 steps per slice)
-    against the GPU's serial F (error in the relative max norm), then two
-    iterations with the numerical G on the 257^2 coarse grid."""
+    against the GPU's serial F (error in the relative max norm), the same with
+    every iteration captured as a hipGraph (capture included in the time), then
+    two iterations with the numerical G on the 257^2 coarse grid."""
     import torch
     from synthetic import largest_single
     inst = largest_single().replace(coarse_steps_per_slice=4)
@@ -287,10 +288,21 @@ def largest_solve(pr):
     t_par = time.perf_counter() - t
     err = float((r.value - ref).abs().max() / ref.abs().max())
     st = r.stats
+    # the same solve with each iteration captured once as a hipGraph and replayed
+    sg = pr.Solver(inst, coarse_kind=pr.PR_G_LOD, flags=pr.PR_FLAG_GRAPH)
+    t = time.perf_counter()
+    rg = sg.solve()
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t
+    err_graph = float((rg.value - ref).abs().max() / ref.abs().max())
+    iters_graph = rg.iters
+    sg.close()
     out = {"workload": "2049^2 FP32 increment form, N=256, T=2, LOD G (4 steps per slice)",
            "workspace_gb": round(sv.workspace_bytes / 2 ** 30, 2),
            "fine_steps_per_slice": st["fine_steps"], "serial_f_s": round(t_ser, 2),
            "parareal_s": round(t_par, 2), "iters": r.iters, "err_vs_serial_f": err,
+           "graph_parareal_s": round(t_graph, 2), "graph_iters": iters_graph,
+           "graph_err_vs_serial_f": err_graph,
            "increments": [float("%.3g" % x) for x in r.increments],
            "step_kernel_gbs": round(st["timed_step_bytes"] / (st["t_step_kernels_ms"] * 1e-3) / 1e9, 1),
            "phase_ms": {"fine": round(st["t_fine_ms"], 1),
