@@ -70,6 +70,7 @@ struct ChainArgs {
     double dt, dT;
     void* gstate;     // 2 nc^2 elements in global memory holding the stepped coarse
                       // state when it does not fit in LDS; nullptr: LDS
+    const double* foldc;   // [slice][nc][nc]: F(U^k_n) at the coincident nodes
 };
 
 }  // namespace pr

@@ -393,7 +393,8 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
 //   c_n+1 = R F(U^k_n) + d_n           (init: c_n+1 = g_n)
 // This is Eq. (parareal) at the coincident nodes: injection after bilinear
 // prolongation returns the coarse values unchanged, so the chain never needs
-// the fine grid except to read F at coincident nodes.
+// the fine grid except F at coincident nodes, which k_gather_coincident has
+// collected into a.foldc before the chain starts.
 // The stepped quantity (FP64 state, or FP32 increments over the FP64 base
 // c_n) is double-buffered in LDS; c_n and the FP32 Lb = L c_n live in global
 // memory (L2-resident).  Each thread owns one coarse column J and a segment of
@@ -406,8 +407,8 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
 // ---------------------------------------------------------------------------
 template <bool CHEAP, bool FP32, int NC, bool GB>
 __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
-    const double* __restrict__ Ucur, const void* __restrict__ Fold, double* __restrict__ Gold,
-    double* __restrict__ dcor, double* __restrict__ cst, float* __restrict__ lbc, ChainArgs a) {
+    const double* __restrict__ Ucur, double* __restrict__ Gold, double* __restrict__ dcor,
+    double* __restrict__ cst, float* __restrict__ lbc, ChainArgs a) {
     using T = typename std::conditional<FP32, float, double>::type;
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
@@ -562,23 +563,15 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
         constexpr int EB = 4;
         for (int r0 = 0; r0 < nr; r0 += EB) {
             double cs[EB], go[EB], fu[EB];
-            float ff[EB];
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
                 const int I = I0 + min(r0 + e, nr - 1), off = I * nc + J;
-                const long long fo = (long long)n * FS + (long long)(I * q - 1) * FP + (J * q - 1);
                 cs[e] = FP32 ? cst[off] : 0.0;
                 go[e] = 0.0;
                 fu[e] = 0.0;
-                ff[e] = 0.f;
                 if (!a.init) {
                     go[e] = Go[off];
-                    if (FP32) {
-                        fu[e] = Ucur[fo];
-                        ff[e] = ((const float*)Fold)[fo];
-                    } else {
-                        fu[e] = ((const double*)Fold)[fo];
-                    }
+                    fu[e] = a.foldc[(long long)n * nn + off];
                 }
             }
 #pragma unroll
@@ -594,8 +587,7 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
                         const double d = g - go[e];
                         Go[off] = g;
                         dc[off] = d;
-                        const double fold = FP32 ? fu[e] + (double)ff[e] : fu[e];
-                        cst[off] = fold + d;
+                        cst[off] = fu[e] + d;   // R F(U^k_n) + d_n
                     }
                 }
             }
@@ -713,6 +705,22 @@ __global__ void k_prolong(const double* __restrict__ Gold, double* __restrict__ 
     U[(long long)(n + 1) * g.stride + (long long)row * g.pitch + jj] =
         (1.0 - al) * (1.0 - be) * c[0] + (1.0 - al) * be * c[1] + al * (1.0 - be) * c[nc] +
         al * be * c[nc + 1];
+}
+
+// F(U^k_n) at the coincident nodes of the coarse interior for slices k0..k1-1,
+// gathered into a dense nc x nc array per slice (the coarse chain then reads it
+// contiguously instead of one strided fine value per node):
+//   foldc[n][I][J] = U^k_n + delta_n (FP32 increments) or w_n (FP64) at fine (I q, J q).
+__global__ void k_gather_coincident(const double* __restrict__ Ucur, const void* __restrict__ Fold,
+                                    double* __restrict__ foldc, Grid g, int nc, int q, int k0,
+                                    int fp32) {
+    const int J = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int I = 1 + blockIdx.y;
+    const int n = k0 + blockIdx.z;
+    if (J > nc - 2) return;
+    const long long fo = (long long)n * g.stride + (long long)(I * q - 1) * g.pitch + (J * q - 1);
+    foldc[(long long)n * nc * nc + I * nc + J] =
+        fp32 ? Ucur[fo] + (double)((const float*)Fold)[fo] : ((const double*)Fold)[fo];
 }
 
 // Interior layout <- full n x n grid (ring ignored).
@@ -855,12 +863,12 @@ bool chain_state_in_lds(int nc, int fp32) {
     return (4 * nc + 2 * nc * nc) * (fp32 ? 4 : 8) <= kChainLdsMax;
 }
 
-hipError_t launch_chain(const double* Ucur, const void* Fold, double* Gold, double* dcor,
-                        double* cst, float* lbc, const ChainArgs& a, hipStream_t st) {
+hipError_t launch_chain(const double* Ucur, double* Gold, double* dcor, double* cst, float* lbc,
+                        const ChainArgs& a, hipStream_t st) {
     const int lds = chain_lds_bytes(a.nc, a.fp32);
 #define PR_CHAIN(C, F, N, G)                                                                \
     hipLaunchKernelGGL((k_coarse_chain<C, F, N, G>), dim3(1), dim3(kChainThreads), lds, st, Ucur, \
-                       Fold, Gold, dcor, cst, lbc, a)
+                       Gold, dcor, cst, lbc, a)
     if (a.gstate) {
         if (a.bc.kind == 2) {
             if (a.fp32) PR_CHAIN(false, true, 0, true); else PR_CHAIN(false, false, 0, true);
@@ -896,6 +904,14 @@ hipError_t launch_zero_red(unsigned long long* red, hipStream_t st) {
 
 hipError_t launch_payoff(double* U, const Grid& g, const Bc& bc, hipStream_t st) {
     hipLaunchKernelGGL(k_payoff, dim3((g.nin + 255) / 256, g.nin), dim3(256), 0, st, U, g, bc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_coincident(const double* Ucur, const void* Fold, double* foldc,
+                                    const Grid& g, int nc, int q, int k0, int k1, int fp32,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_coincident, dim3((nc - 2 + 255) / 256, nc - 2, k1 - k0), dim3(256),
+                       0, st, Ucur, Fold, foldc, g, nc, q, k0, fp32);
     return hipGetLastError();
 }
 

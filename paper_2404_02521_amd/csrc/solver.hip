@@ -29,8 +29,10 @@ hipError_t launch_fine_prep(const double*, float*, float*, const StepArgs&, hipS
 hipError_t launch_fine_tb_f32(const float*, const float*, float*, const StepArgs&, int, hipStream_t);
 hipError_t launch_fine_tb_f64(const double*, double*, const StepArgs&, int, hipStream_t);
 hipError_t chain_set_lds(int);
-hipError_t launch_chain(const double*, const void*, double*, double*, double*, float*,
-                        const ChainArgs&, hipStream_t);
+hipError_t launch_chain(const double*, double*, double*, double*, float*, const ChainArgs&,
+                        hipStream_t);
+hipError_t launch_gather_coincident(const double*, const void*, double*, const Grid&, int, int,
+                                    int, int, int, hipStream_t);
 int chain_lds_bytes(int, int);
 bool chain_state_in_lds(int, int);
 hipError_t launch_correct(const double*, const void*, const double*, const double*, double*,
@@ -103,7 +105,7 @@ double gershgorin_dt(int n, const pr_model& m) {
 struct Layout {
     uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
         lw0, lw1, lwb, Sr, Sp, fwf, fT, fwc, fwc1, fTp, fin, fmeta, fout, fvc0, fvc1, flw0, flw1,
-        flwb, fwb, gst, total;
+        flwb, fwb, gst, foldc, total;
 };
 
 bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
@@ -157,6 +159,7 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.Gold = take(N * nc * nc * 8);
     L.dcor = take(N * nc * nc * 8);
     L.cst = take(nc * nc * 8);
+    L.foldc = take(N * nc * nc * 8);
     L.lbc = take(nc * nc * 4);
     // chain state in global memory when it does not fit in LDS
     L.gst = take(nc > 0 && !chain_state_in_lds((int)nc, fp32 ? 1 : 0) ? 2 * nc * nc * (fp32 ? 4 : 8)
@@ -387,6 +390,7 @@ ChainArgs chain_args(pr_solver* s, int k0, int k1, int init) {
     a.dt = s->dtG;
     a.dT = s->dT;
     a.gstate = chain_state_in_lds(s->nc, a.fp32) ? nullptr : (void*)s->at<char>(s->L.gst);
+    a.foldc = s->at<double>(s->L.foldc);
     return a;
 }
 
@@ -579,7 +583,7 @@ pr_status init_phase(pr_solver* s, double* Ucur, double* Unext) {
         }
     } else {
         ChainArgs ca = chain_args(s, 0, N, 1);
-        HIPCHK(launch_chain(Ucur, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+        HIPCHK(launch_chain(Ucur, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
                             s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
         HIPCHK(launch_prolong(s->at<double>(s->L.Gold), Ucur, g, s->nc, s->q, 0, N, s->stream));
     }
@@ -616,7 +620,9 @@ pr_status iteration_phase(pr_solver* s, int k, double* Ucur, double* Unext, doub
         if (ev) HIPCHK(hipEventRecord(s->ev[2], s->stream));
     } else {
         ChainArgs ca = chain_args(s, k, N, 0);
-        HIPCHK(launch_chain(Ucur, Fold, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+        HIPCHK(launch_gather_coincident(Ucur, Fold, s->at<double>(s->L.foldc), g, s->nc, s->q, k,
+                                        N, s->fp32 ? 1 : 0, s->stream));
+        HIPCHK(launch_chain(Ucur, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
                             s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
         if (ev) HIPCHK(hipEventRecord(s->ev[2], s->stream));
         HIPCHK(launch_correct(Ucur, Fold, s->at<double>(s->L.dcor), nullptr, nullptr, Unext, red,
@@ -1045,7 +1051,7 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
         if (r != PR_OK) return r;
     } else {
         ChainArgs ca = chain_args(s, slice, slice + 1, 1);
-        HIPCHK(launch_chain(U, nullptr, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+        HIPCHK(launch_chain(U, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
                             s->at<double>(s->L.cst), s->at<float>(s->L.lbc), ca, s->stream));
         HIPCHK(launch_prolong(s->at<double>(s->L.Gold), U, g, s->nc, s->q, slice, slice + 1,
                               s->stream));
