@@ -6,8 +6,13 @@
 //                  (d+ = d + dt (Lb + L d) over an FP64 base b), and the FP32
 //                  preparation step that evaluates Lb = L b in FP64 and writes
 //                  the first increment dt*Lb.
+//  k_fine_tb     : S explicit steps of the same operator per launch
+//                  (temporal blocking in registers), the hot kernel of F.
 //  k_coarse_chain: the serial sweep of Eq. (parareal) (Sec. 3.1) restricted
-//                  to the coarse grid, one workgroup, coarse state in LDS.
+//                  to the coarse grid, one workgroup, coarse state in LDS (in
+//                  global memory when it does not fit).
+//  k_gather_coincident: F(U^k_n) at the coarse nodes for all active slices,
+//                  ahead of the chain.
 //  k_correct     : U^{k+1}_{n+1} = F(U^k_n) + P(Gc_new - Gc_old) in FP64 over
 //                  all active slices, fused with the max-increment reduction.
 //  small kernels : payoff, prolongation of the initial sweep, pack / unpack
