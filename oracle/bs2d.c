@@ -15,7 +15,7 @@
  *   - the centred finite-difference operator of Eq. (fd), Sec. 3.2 (second
  *     differences in x and y, the four-corner mixed difference, centred first
  *     differences, reaction -r u), written with x_i = i*h so that h cancels;
- *   - explicit Euler in time (the fine propagator of this build; the paper
+ *   - explicit Euler in time (the fine propagator used here; the paper
  *     uses implicit Euler, Eq. (fd), which is a later extension);
  *   - the coarse propagator G = B o P o Gc o R (injection, coarse explicit
  *     steps, bilinear prolongation, exact Dirichlet ring);

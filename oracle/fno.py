@@ -2,7 +2,7 @@
 
 Follows Sec. 3.4 (FNO: lifting, Fourier layers of truncated-mode multipliers
 plus a pointwise path, projection) and Sec. 3.5 (physics-informed loss), with
-the sizes of this build: width 32, four Fourier layers, 12 x 12 retained modes
+the sizes used here: width 32, four Fourier layers, 12 x 12 retained modes
 on a 64 x 64 grid, GELU, two-layer lift (C_in -> 64 -> 32) and projection
 (32 -> 128 -> 1).  Gradients are derived by hand and pinned against central
 differences in the tests.

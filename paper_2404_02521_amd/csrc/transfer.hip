@@ -8,7 +8,8 @@
 // evaluates them on the 62 x 62 interior of the 64 x 64 grid, prolongation
 // zero-pads the 62 modes back to the fine grid.  Both are separable, so each
 // is two FP64 matrix products with host-built (62 x nf) / (nf x 62) matrices
-// (Sec. 3.4 runs the operator on its own grid; the transfer is this build's).
+// (Sec. 3.4 runs the operator on its own grid; the transfer to and from the
+// fine grid is an addition of this library).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
