@@ -115,6 +115,40 @@ def test_exact_bc_fp64(pr):
     assert abs_max(gpu, ref) <= FP64_TOL
 
 
+@pytest.mark.parametrize("M", [131, 257])
+def test_exact_bc_fp32(pr, M):
+    """Margrabe ring (exchange) in the FP32 increment form: the closed-form ring
+    values of the edge strips' row path (evaluated three rows at a time across
+    lanes) and of the ring rows, against the oracle's serial F."""
+    inst = plain_fp64(EXCHANGE).replace(M=M, fp32=True, fine_steps_per_slice=0,
+                                        coarse_steps_per_slice=0, T=0.05, n_slices=2,
+                                        coarse_M=(M - 1) // 2 + 1)
+    mf, _, _, _ = pr.plan(inst)
+    say("exact bc fp32", M, mf)
+    s = pr.Solver(inst, bc_kind=pr.PR_BC_EXACT)
+    gpu = host(s.serial_fine().value)
+    ref = oracle.serial_fine(oproblem(inst, bc_kind=oracle.BC_EXACT), 2, inst.T, mf)
+    assert rel_max(gpu, ref) <= FP32_TOL
+    s.close()
+
+
+@pytest.mark.parametrize("M", [5, 33, 67])
+def test_narrow_grids_fp32(pr, M):
+    """Grids narrower than a wavefront strip (both ring columns in one strip, the
+    general row path throughout) and one just wider, FP32 increment form, serial F
+    against the oracle."""
+    inst = plain_fp64(BASKET).replace(M=M, fp32=True, fine_steps_per_slice=0,
+                                      coarse_steps_per_slice=0, T=0.2, n_slices=2,
+                                      coarse_M=(M - 1) // 2 + 1)
+    mf, _, _, _ = pr.plan(inst)
+    say("narrow fp32", M, mf)
+    s = pr.Solver(inst)
+    gpu = host(s.serial_fine().value)
+    ref = oracle.serial_fine(oproblem(inst), 2, inst.T, mf)
+    assert rel_max(gpu, ref) <= FP32_TOL
+    s.close()
+
+
 # ---------------------------------------------------------------- Parareal, FP64
 @pytest.mark.parametrize("payoff", [BASKET, EXCHANGE])
 @pytest.mark.parametrize("k", [1, 2, 3])
