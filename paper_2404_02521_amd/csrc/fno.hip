@@ -513,6 +513,19 @@ __global__ __launch_bounds__(256) void k_loss3(const double* __restrict__ part, 
 }
 
 // Adam (Kingma and Ba) over the flat parameter vector; c1 = 1 - b1^t, c2 = 1 - b2^t.
+// out[g][c] = sum of in[s][c] over s in [g * per, min((g + 1) * per, S)), in
+// order of s (rows of W floats); grid (ceil(W / 256), groups).
+__global__ void k_colsum(const float* __restrict__ in, int S, int W, int per,
+                         float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (c >= W) return;
+    const int s1 = min((g + 1) * per, S);
+    float acc = 0.f;
+    for (int s = g * per; s < s1; ++s) acc += in[(long long)s * W + c];
+    out[(long long)g * W + c] = acc;
+}
+
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
                        float c1, float c2) {
@@ -559,12 +572,17 @@ struct ParamIndex {
     }
 };
 
-constexpr int kSplits = 256;   // split-K factor of the weight-gradient reductions
+// Weight-gradient reductions over the Q = batch x 4096 nodes are split into
+// chunks of kSplitRows nodes (one product per chunk, many workgroups in
+// flight), then the chunk partials are summed in a fixed order in groups of
+// kSumGroup and the group sums again.
+constexpr int kSplitRows = 128;
+constexpr int kSumGroup = 32;
 
 struct Layout {
     uint64_t params, grads, m, v, Rs, gRs, tabs, offs, ones;
     uint64_t inp, z1, h1, vv[NL], zz[NL], T1, X[NL], Y, Z, zq, hq, out;
-    uint64_t gA, gB, gbig, gT, gX, gY, part, gpred, cc, lpart, lres;
+    uint64_t gA, gB, gbig, gT, gX, gY, part, part2, gpred, cc, lpart, lres;
     uint64_t total;
 };
 
@@ -602,7 +620,10 @@ Layout make_layout(int Bm) {
     L.gT = take((uint64_t)Bm * G * 2 * MX * C * f);
     L.gX = take((uint64_t)NMODE * Bm * 2 * C * f);
     L.gY = take((uint64_t)Bm * 2 * NMODE * C * f);
-    L.part = take((uint64_t)kSplits * (C + 1) * PH * f);   // largest (K+1) x N: P1 and p1
+    // largest (K+1) x N: P1 and p1
+    const uint64_t nsplit = (Q + kSplitRows - 1) / kSplitRows;
+    L.part = take(nsplit * (C + 1) * PH * f);
+    L.part2 = take((nsplit + kSumGroup - 1) / kSumGroup * (C + 1) * PH * f);
     L.gpred = take(Q * f);
     L.cc = take(Q * f);
     L.lpart = take((uint64_t)Bm * G * 2 * 8);
@@ -717,7 +738,7 @@ hipError_t dense(pr_fno* f, const float* in, int K, const float* W, const float*
 hipError_t wgrad(pr_fno* f, const float* in, int K, const float* g, int N, float* dst,
                  long long Q, bool mf, bool bias = true) {
     const int KB = bias ? K + 1 : K;   // rows of the product; row K reads ones
-    const long long kc = (Q + kSplits - 1) / kSplits;
+    const long long kc = kSplitRows;
     const int S = (int)((Q + kc - 1) / kc);
     float* part = f->at(f->L.part);
     // the last split may be short: K bounds are per split, so run the full
@@ -737,9 +758,14 @@ hipError_t wgrad(pr_fno* f, const float* in, int K, const float* g, int N, float
         if (bias) a.ones(K);
         TRY(run(a, mf, f->st));
     }
-    Gemm<float> r(1, KB * N, S);
-    r.A(f->ones, 0, 0).B(part, (long long)KB * N, 1).Cm(dst, 0, 1);
-    return run(r, false, f->st);
+    // dst = sum over the S partials (KB * N each), in a fixed order
+    const int W = KB * N, NG = (S + kSumGroup - 1) / kSumGroup;
+    float* part2 = f->at(f->L.part2);
+    hipLaunchKernelGGL(k_colsum, dim3((W + 255) / 256, NG), dim3(256), 0, f->st, part, S, W,
+                       kSumGroup, part2);
+    hipLaunchKernelGGL(k_colsum, dim3((W + 255) / 256, 1), dim3(256), 0, f->st, part2, NG, W, NG,
+                       dst);
+    return hipGetLastError();
 }
 
 // Spectral convolution of layer l, accumulated onto z (which holds v W + b);
