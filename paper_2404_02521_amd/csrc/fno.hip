@@ -520,9 +520,18 @@ __global__ void k_colsum(const float* __restrict__ in, int S, int W, int per,
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int g = blockIdx.y;
     if (c >= W) return;
-    const int s1 = min((g + 1) * per, S);
+    const int s0 = g * per, s1 = min((g + 1) * per, S);
     float acc = 0.f;
-    for (int s = g * per; s < s1; ++s) acc += in[(long long)s * W + c];
+    int s = s0;
+    // eight loads in flight per round; the adds stay in the order of s
+    for (; s + 8 <= s1; s += 8) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = in[(long long)(s + e) * W + c];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc += v[e];
+    }
+    for (; s < s1; ++s) acc += in[(long long)s * W + c];
     out[(long long)g * W + c] = acc;
 }
 
