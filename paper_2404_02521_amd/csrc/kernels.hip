@@ -612,6 +612,7 @@ __global__ __launch_bounds__(kChainThreads) void k_coarse_chain(
 struct CorrArgs {
     Grid g;
     int k0, k1, N, nc, q, fp32, fineg;
+    int rows;   // interior rows per workgroup
 };
 
 __device__ inline void wave_max2(double& a, double& b) {
@@ -633,41 +634,44 @@ __global__ __launch_bounds__(kBlock) void k_correct(const double* __restrict__ U
     __shared__ int sflag;
     if (threadIdx.x == 0) sflag = 0;
     const int nin = a.g.nin;
-    const int segs = (nin + kBlock - 1) / kBlock;
-    const int row = blockIdx.x / segs;
-    const int jj = (blockIdx.x % segs) * kBlock + threadIdx.x;   // 0-based interior column
     const int n = a.k0 + blockIdx.y;
+    // a workgroup takes a.rows rows of one slice, so that the per-workgroup
+    // reduction (and its global atomics) is paid once per a.rows * nin nodes
+    const int r0 = blockIdx.x * a.rows, r1 = min(r0 + a.rows, nin);
     double inc = 0.0, sc = 0.0;
     int bad = 0;
     __syncthreads();
-    if (jj < nin) {
-        const int i = row + 1, j = jj + 1;
-        const long long o = (long long)row * a.g.pitch + jj;
-        const long long on = (long long)n * a.g.stride + o;
-        const long long on1 = (long long)(n + 1) * a.g.stride + o;
-        const double fo = a.fp32 ? Ucur[on] + (double)((const float*)Fold)[on]
-                                 : ((const double*)Fold)[on];
-        double corr;
-        if (a.fineg) {
-            const long long ol = o;   // gfine holds one slice
-            const double g = gfine[ol];
-            corr = g - Gf[on];
-            Gf[on] = g;
-        } else {
-            const int q = a.q, nc = a.nc;
-            const int I = i / q, J = j / q;
-            const double al = (double)(i - I * q) / (double)q;
-            const double be = (double)(j - J * q) / (double)q;
-            const double* d = dcor + (long long)n * nc * nc + I * nc + J;
-            corr = (1.0 - al) * (1.0 - be) * d[0] + (1.0 - al) * be * d[1] +
-                   al * (1.0 - be) * d[nc] + al * be * d[nc + 1];
+    for (int row = r0; row < r1; ++row) {
+        for (int jj = threadIdx.x; jj < nin; jj += kBlock) {   // 0-based interior column
+            const int i = row + 1, j = jj + 1;
+            const long long o = (long long)row * a.g.pitch + jj;
+            const long long on = (long long)n * a.g.stride + o;
+            const long long on1 = (long long)(n + 1) * a.g.stride + o;
+            const double fo = a.fp32 ? Ucur[on] + (double)((const float*)Fold)[on]
+                                     : ((const double*)Fold)[on];
+            double corr;
+            if (a.fineg) {
+                const long long ol = o;   // gfine holds one slice
+                const double g = gfine[ol];
+                corr = g - Gf[on];
+                Gf[on] = g;
+            } else {
+                const int q = a.q, nc = a.nc;
+                const int I = i / q, J = j / q;
+                const double al = (double)(i - I * q) / (double)q;
+                const double be = (double)(j - J * q) / (double)q;
+                const double* d = dcor + (long long)n * nc * nc + I * nc + J;
+                corr = (1.0 - al) * (1.0 - be) * d[0] + (1.0 - al) * be * d[1] +
+                       al * (1.0 - be) * d[nc] + al * be * d[nc + 1];
+            }
+            const double v = fo + corr;
+            const double old = Ucur[on1];
+            Unext[on1] = v;
+            const double dv = fabs(v - old);
+            if (!(dv <= DBL_MAX)) bad = 1;
+            inc = fmax(inc, dv);
+            if (n + 1 == a.N) sc = fmax(sc, fabs(v));
         }
-        const double v = fo + corr;
-        const double old = Ucur[on1];
-        Unext[on1] = v;
-        inc = fabs(v - old);
-        if (!(inc <= DBL_MAX)) bad = 1;
-        if (n + 1 == a.N) sc = fabs(v);
     }
     if (bad) sflag = 1;   // benign race: every writer stores 1
     wave_max2(inc, sc);
@@ -895,10 +899,12 @@ hipError_t launch_correct(const double* Ucur, const void* Fold, const double* dc
                           const double* gfine, double* Gf, double* Unext,
                           unsigned long long* red, const Grid& g, int k0, int k1, int N, int nc,
                           int q, int fp32, int fineg, hipStream_t st) {
-    CorrArgs a{g, k0, k1, N, nc, q, fp32, fineg};
-    const int segs = (g.nin + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_correct, dim3(g.nin * segs, k1 - k0), dim3(kBlock), 0, st, Ucur, Fold,
-                       dcor, gfine, Gf, Unext, red, a);
+    // rows per workgroup: about 2048 workgroups per launch, at least one row
+    const long long nodes = (long long)g.nin * g.nin * (k1 - k0);
+    const int rows = (int)std::max<long long>(1, std::min<long long>(g.nin, nodes / (2048LL * kBlock * 4)));
+    CorrArgs a{g, k0, k1, N, nc, q, fp32, fineg, rows};
+    hipLaunchKernelGGL(k_correct, dim3((g.nin + rows - 1) / rows, k1 - k0), dim3(kBlock), 0, st,
+                       Ucur, Fold, dcor, gfine, Gf, Unext, red, a);
     return hipGetLastError();
 }
 
