@@ -52,6 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
                                                       const float* __restrict__ lb,
                                                       TO* __restrict__ out,
                                                       float* __restrict__ out2, StepArgs a) {
+#pragma clang fp contract(on)
     const int lane = threadIdx.x & 63;
     const int wid = xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) + (threadIdx.x >> 6);
     const int strip = wid % a.nstrips;
@@ -168,6 +169,10 @@ template <int MODE, bool CHEAP, typename T, int S, int PF>
 __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                                                     const float* __restrict__ lb,
                                                     T* __restrict__ out, StepArgs a) {
+    // multiply-adds are fused only within a statement, so every instance (S,
+    // row path) evaluates a point-step with the same roundings: the result does
+    // not depend on the launch geometry
+#pragma clang fp contract(on)
     constexpr int W = kWave - 2 * S;
     static_assert(S < 32, "ring lanes: columns 0 and M-1 use lanes 0..S and 32..32+S");
     const int lane = threadIdx.x & 63;

@@ -105,6 +105,26 @@ def test_every_fused_step_count(pr, monkeypatch, fuse, fp32):
     s.close()
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_launch_geometry_is_bitwise_invisible(pr, monkeypatch, fp32):
+    """Every point-step is the same expression whatever the launch geometry, so
+    serial F is bitwise the same for every fused-step count S and row-chunk size
+    (interior, one-ring-column and general row paths, remainder launches)."""
+    inst = plain_fp64(BASKET).replace(M=131, coarse_M=27, n_slices=2, fine_steps_per_slice=0,
+                                      coarse_steps_per_slice=0, T=0.03, fp32=fp32)
+    outs = []
+    for fuse, rows in [(1, 0), (3, 0), (6, 0), (8, 0), (6, 5), (4, 64)]:
+        monkeypatch.setenv("PR_STEP_FUSE", str(fuse))
+        monkeypatch.setenv("PR_STEP_SMALL_COUNT", "0")
+        monkeypatch.setenv("PR_STEP_ROWS", str(rows))
+        say("launch geometry", fp32, fuse, rows)
+        s = pr.Solver(inst)
+        outs.append(host(s.serial_fine().value))
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_exact_bc_fp64(pr):
     """Margrabe ring (exchange) through the closed-form ring path."""
     inst = plain_fp64(EXCHANGE)
