@@ -210,6 +210,22 @@ def test_finite_termination_bitwise(pr, fp32):
 
 
 @pytest.mark.parametrize("fp32", [False, True])
+def test_finite_termination_bitwise_mixed_fused_steps(pr, monkeypatch, fp32):
+    """With sweeps of <= 4 slices (and serial F) on S = 3 and larger sweeps on
+    S = 6, Parareal after N iterations still equals serial F bitwise."""
+    monkeypatch.setenv("PR_STEP_FUSE", "6")
+    monkeypatch.setenv("PR_STEP_FUSE_SMALL", "3")
+    monkeypatch.setenv("PR_STEP_SMALL_COUNT", "4")
+    inst = plain_fp64(BASKET).replace(tol=0.0, fp32=fp32)
+    say("finite termination mixed S", fp32)
+    s = pr.Solver(inst)
+    res = s.solve()
+    assert res.iters == inst.n_slices
+    assert np.array_equal(host(res.value), host(s.serial_fine().value))
+    s.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
 def test_G_equal_F_one_iteration(pr, fp32):
     inst = plain_fp64(EXCHANGE).replace(fp32=fp32)
     say("G=F", fp32)
