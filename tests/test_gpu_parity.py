@@ -135,6 +135,32 @@ def test_exact_bc_fp64(pr):
     assert abs_max(gpu, ref) <= FP64_TOL
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_discounted_payoff_bc(pr, fp32):
+    """The literal discounted-payoff ring (e^{-r tau} times the payoff) through
+    serial F and two Parareal iterations, against the oracle."""
+    inst = plain_fp64(BASKET).replace(M=131, coarse_M=33, fine_steps_per_slice=0,
+                                      coarse_steps_per_slice=0, T=0.25, n_slices=4, tol=0.0,
+                                      fp32=fp32)
+    mf, mg, _, _ = pr.plan(inst)
+    say("discounted payoff bc", fp32, mf, mg)
+    s = pr.Solver(inst, bc_kind=pr.PR_BC_DISCOUNTED_PAYOFF, max_iters=2)
+    pf = oproblem(inst, bc_kind=oracle.BC_DISCOUNTED_PAYOFF)
+    pc = oproblem(inst, inst.coarse_M, bc_kind=oracle.BC_DISCOUNTED_PAYOFF)
+    ser = host(s.serial_fine().value)
+    ref = oracle.serial_fine(pf, 4, inst.T, mf)
+    res = s.solve()
+    U, K, _ = oracle.parareal_bs(pf, pc, 4, inst.T, mf, mg, max_iters=2, tol=0.0)
+    assert res.iters == K == 2
+    if fp32:
+        assert rel_max(ser, ref) <= FP32_TOL
+        assert rel_max(host(res.value), U) <= FP32_TOL
+    else:
+        assert abs_max(ser, ref) <= FP64_TOL
+        assert abs_max(host(res.value), U) <= FP64_TOL
+    s.close()
+
+
 @pytest.mark.parametrize("M", [131, 257])
 def test_exact_bc_fp32(pr, M):
     """Margrabe ring (exchange) in the FP32 increment form: the closed-form ring
