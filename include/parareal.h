@@ -406,6 +406,38 @@ pr_status pr_fno_adam(pr_fno* f, double lr, int32_t step);
 pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, int64_t n_pairs,
                             const int32_t* idx, int32_t batch, double dT, double lam, double lr,
                             int32_t step, int32_t precision, double* host_loss);
+/* Weight files: the trained network reused without retraining, across
+ * processes and runs (Sec. 4.4 and Sec. 4.5 apply the trained operator to other
+ * resolutions and parameters without retraining it).  A file holds a 96-byte
+ * header (magic "PRFNOW01", version, the architecture constants above, base,
+ * inference precision, out_scale, parameter count, a caller-chosen 64-bit hash
+ * of the training configuration, an FNV-1a 64 checksum of header and weights)
+ * followed by the flat FP32 master weights.
+ *
+ * pr_fno_save: copies the handle's parameters to the host (synchronises its
+ * stream) and writes path atomically (path.tmp, then rename).  PR_EMODEL when
+ * the file cannot be written.
+ * pr_fno_check_file (host only, no GPU): validates a file (magic, version,
+ * architecture, parameter count, field ranges, checksum, finite weights, no
+ * trailing bytes) and fills info (may be NULL).  PR_EMODEL, with no further
+ * detail, for a missing, truncated, corrupted or incompatible file.
+ * pr_fno_load: validates as pr_fno_check_file, then requires the file's base and
+ * out_scale to equal the handle's configuration (PR_EMODEL otherwise, with a
+ * message in pr_fno_last_error), copies the weights in and clears the Adam
+ * moments as pr_fno_set_params does; synchronises the handle's stream.  The
+ * handle is unchanged when the call fails. */
+typedef struct {
+    uint32_t version;
+    int32_t base;         /* PR_FNO_BASE_* the weights were trained for */
+    int32_t precision;    /* PR_FNO_* inference precision of the saving handle */
+    int32_t pad_;
+    double out_scale;
+    uint64_t param_count;
+    uint64_t train_hash;  /* the value given to pr_fno_save */
+} pr_fno_file_info;
+pr_status pr_fno_save(pr_fno* f, const char* path, uint64_t train_hash);
+pr_status pr_fno_check_file(const char* path, pr_fno_file_info* info);
+pr_status pr_fno_load(pr_fno* f, const char* path, pr_fno_file_info* info);
 pr_status pr_fno_destroy(pr_fno* f);
 const char* pr_fno_last_error(const pr_fno* f);
 

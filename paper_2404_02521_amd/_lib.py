@@ -73,6 +73,12 @@ class pr_fno_config(C.Structure):
                 ("base", C.c_int32), ("pad_", C.c_int32)]
 
 
+class pr_fno_file_info(C.Structure):
+    _fields_ = [("version", C.c_uint32), ("base", C.c_int32), ("precision", C.c_int32),
+                ("pad_", C.c_int32), ("out_scale", C.c_double), ("param_count", C.c_uint64),
+                ("train_hash", C.c_uint64)]
+
+
 class pr_request_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("last_increment", C.c_double),
                 ("latency_ms", C.c_double), ("queue_ms", C.c_double),
@@ -128,6 +134,9 @@ SIGNATURES = [
     ("pr_fno_train_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                     C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32,
                                     C.c_int32, C.POINTER(C.c_double)]),
+    ("pr_fno_save", C.c_int, [C.c_void_p, C.c_char_p, C.c_uint64]),
+    ("pr_fno_check_file", C.c_int, [C.c_char_p, C.POINTER(pr_fno_file_info)]),
+    ("pr_fno_load", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(pr_fno_file_info)]),
     ("pr_fno_destroy", C.c_int, [C.c_void_p]),
     ("pr_fno_last_error", C.c_char_p, [C.c_void_p]),
 ]

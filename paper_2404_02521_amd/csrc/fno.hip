@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -1157,6 +1158,151 @@ pr_status pr_fno_train_step(pr_fno* f, const float* pairs, const float* meta, in
                                hipMemcpyDeviceToHost, f->st));
         FNO_HIP(hipStreamSynchronize(f->st));
     }
+    return PR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Weight file (pr_fno_save / pr_fno_load / pr_fno_check_file).  Little-endian:
+//   [0, 8)   magic "PRFNOW01"
+//   [8, 12)  uint32 version (1)            [12, 16) uint32 header bytes (96)
+//   [16, 44) int32 grid, width, modes, layers, c_in, lift, proj
+//   [44, 48) int32 base                    [48, 52) int32 inference precision
+//   [52, 56) int32 0                       [56, 64) double out_scale
+//   [64, 72) uint64 parameter count        [72, 80) uint64 training-config hash
+//   [80, 88) uint64 FNV-1a 64 of bytes [0, 80) followed by the parameters
+//   [88, 96) uint64 0
+//   [96, ..) parameter count FP32 master weights (the flat vector of set_params)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr char kFileMagic[8] = {'P', 'R', 'F', 'N', 'O', 'W', '0', '1'};
+constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileHeader = 96;
+
+uint64_t fnv1a(uint64_t h, const unsigned char* p, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+const int32_t kArch[7] = {PR_FNO_GRID, PR_FNO_WIDTH, PR_FNO_MODES, PR_FNO_LAYERS,
+                          PR_FNO_CIN, PR_FNO_LIFT, PR_FNO_PROJ};
+
+// Reads and validates a weight file; params receives the weights when non-null.
+pr_status read_weight_file(const char* path, pr_fno_file_info* info, std::vector<float>* params,
+                           std::string* why) {
+    auto bad = [&](const std::string& m) { if (why) *why = m; return PR_EMODEL; };
+    if (!path) return bad("null path");
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return bad(std::string("cannot open ") + path);
+    unsigned char hdr[kFileHeader];
+    const size_t got = std::fread(hdr, 1, kFileHeader, fp);
+    if (got != kFileHeader) { std::fclose(fp); return bad("truncated header"); }
+    if (std::memcmp(hdr, kFileMagic, 8) != 0) { std::fclose(fp); return bad("not an FNO weight file (magic)"); }
+    uint32_t ver, hb;
+    int32_t arch[7], base, prec;
+    double scale;
+    uint64_t count, thash, sum;
+    std::memcpy(&ver, hdr + 8, 4);
+    std::memcpy(&hb, hdr + 12, 4);
+    std::memcpy(arch, hdr + 16, 28);
+    std::memcpy(&base, hdr + 44, 4);
+    std::memcpy(&prec, hdr + 48, 4);
+    std::memcpy(&scale, hdr + 56, 8);
+    std::memcpy(&count, hdr + 64, 8);
+    std::memcpy(&thash, hdr + 72, 8);
+    std::memcpy(&sum, hdr + 80, 8);
+    if (ver != kFileVersion || hb != kFileHeader) { std::fclose(fp); return bad("unsupported file version"); }
+    if (std::memcmp(arch, kArch, sizeof(kArch)) != 0) { std::fclose(fp); return bad("architecture differs from this library's"); }
+    if (count != (uint64_t)ParamIndex().total) { std::fclose(fp); return bad("parameter count differs"); }
+    if (base < PR_FNO_BASE_ZERO || base > PR_FNO_BASE_FINE_LOD || !valid_prec(prec) ||
+        !(scale > 0.0) || !std::isfinite(scale)) {
+        std::fclose(fp);
+        return bad("invalid header field");
+    }
+    std::vector<float> w(count);
+    const size_t gw = std::fread(w.data(), sizeof(float), count, fp);
+    unsigned char extra;
+    const bool trailing = std::fread(&extra, 1, 1, fp) == 1;
+    std::fclose(fp);
+    if (gw != count) return bad("truncated parameters");
+    if (trailing) return bad("trailing bytes after the parameters");
+    uint64_t h = fnv1a(1469598103934665603ull, hdr, 80);
+    h = fnv1a(h, reinterpret_cast<const unsigned char*>(w.data()), count * sizeof(float));
+    if (h != sum) return bad("checksum mismatch");
+    for (float v : w)
+        if (!std::isfinite(v)) return bad("non-finite parameter");
+    if (info) {
+        info->version = ver;
+        info->base = base;
+        info->precision = prec;
+        info->pad_ = 0;
+        info->out_scale = scale;
+        info->param_count = count;
+        info->train_hash = thash;
+    }
+    if (params) params->swap(w);
+    return PR_OK;
+}
+
+}  // namespace
+
+pr_status pr_fno_check_file(const char* path, pr_fno_file_info* info) {
+    return read_weight_file(path, info, nullptr, nullptr);
+}
+
+pr_status pr_fno_save(pr_fno* f, const char* path, uint64_t train_hash) {
+    if (!f || !path) return PR_EINVAL;
+    const uint64_t count = (uint64_t)f->pi.total;
+    std::vector<float> w(count);
+    FNO_HIP(hipMemcpyAsync(w.data(), f->params, count * sizeof(float), hipMemcpyDeviceToHost, f->st));
+    FNO_HIP(hipStreamSynchronize(f->st));
+    unsigned char hdr[kFileHeader];
+    std::memset(hdr, 0, sizeof(hdr));
+    const int32_t base = f->base, prec = f->infer_prec;
+    const double scale = f->out_scale;
+    std::memcpy(hdr, kFileMagic, 8);
+    std::memcpy(hdr + 8, &kFileVersion, 4);
+    std::memcpy(hdr + 12, &kFileHeader, 4);
+    std::memcpy(hdr + 16, kArch, 28);
+    std::memcpy(hdr + 44, &base, 4);
+    std::memcpy(hdr + 48, &prec, 4);
+    std::memcpy(hdr + 56, &scale, 8);
+    std::memcpy(hdr + 64, &count, 8);
+    std::memcpy(hdr + 72, &train_hash, 8);
+    uint64_t h = fnv1a(1469598103934665603ull, hdr, 80);
+    h = fnv1a(h, reinterpret_cast<const unsigned char*>(w.data()), count * sizeof(float));
+    std::memcpy(hdr + 80, &h, 8);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "wb");
+    if (!fp) return fail(f, PR_EMODEL, "cannot create " + tmp);
+    bool ok = std::fwrite(hdr, 1, kFileHeader, fp) == kFileHeader &&
+              std::fwrite(w.data(), sizeof(float), count, fp) == count;
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(f, PR_EMODEL, std::string("cannot write ") + path);
+    }
+    return PR_OK;
+}
+
+pr_status pr_fno_load(pr_fno* f, const char* path, pr_fno_file_info* info) {
+    if (!f || !path) return PR_EINVAL;
+    pr_fno_file_info fi{};
+    std::vector<float> w;
+    std::string why;
+    const pr_status st = read_weight_file(path, &fi, &w, &why);
+    if (st != PR_OK) return fail(f, st, why);
+    if (fi.base != f->base || fi.out_scale != f->out_scale)
+        return fail(f, PR_EMODEL, "the file's base or out_scale differs from the handle's configuration");
+    FNO_HIP(hipMemcpyAsync(f->params, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice, f->st));
+    FNO_HIP(hipMemsetAsync(f->at(f->L.m), 0, (f->L.v - f->L.m) + f->pi.total * 4, f->st));
+    FNO_HIP(hipStreamSynchronize(f->st));
+    f->stacked = false;
+    f->fwd_batch = 0;
+    if (info) *info = fi;
     return PR_OK;
 }
 

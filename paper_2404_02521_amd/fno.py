@@ -6,6 +6,7 @@ torch provides the workspace, the tensors and the stream.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 from . import _lib as L
 
@@ -24,6 +25,20 @@ def _check(st: int, what: str, handle=None) -> None:
 
 def param_count() -> int:
     return int(L.lib().pr_fno_param_count())
+
+
+def _info_dict(info) -> dict:
+    return dict(version=info.version, base=info.base, precision=info.precision,
+                out_scale=info.out_scale, param_count=info.param_count,
+                train_hash=info.train_hash)
+
+
+def check_file(path: str) -> dict:
+    """Validate a weight file on the host (no GPU); raises PararealError(PR_EMODEL)
+    for a missing, truncated, corrupted or incompatible file."""
+    info = L.pr_fno_file_info()
+    _check(L.lib().pr_fno_check_file(os.fsencode(path), C.byref(info)), "pr_fno_check_file")
+    return _info_dict(info)
 
 
 def _ptr(t, dtype, shape=None):
@@ -82,6 +97,19 @@ class Fno:
                "pr_fno_get_grads", self.handle)
         self.stream.synchronize()
         return out
+
+    # -- weight files -----------------------------------------------------------
+    def save(self, path: str, train_hash: int = 0) -> None:
+        """Write the FP32 master weights with the header of pr_fno_save."""
+        _check(L.lib().pr_fno_save(self.handle, os.fsencode(path), C.c_uint64(train_hash)),
+               "pr_fno_save", self.handle)
+
+    def load(self, path: str) -> dict:
+        """Read weights written by save (validated first); returns the file's header."""
+        info = L.pr_fno_file_info()
+        _check(L.lib().pr_fno_load(self.handle, os.fsencode(path), C.byref(info)),
+               "pr_fno_load", self.handle)
+        return _info_dict(info)
 
     # -- compute --------------------------------------------------------------
     def forward(self, w, meta, precision: int = L.PR_FNO_FP32):

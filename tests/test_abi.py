@@ -36,7 +36,7 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"pr_grid": L.pr_grid, "pr_model": L.pr_model, "pr_payoff": L.pr_payoff,
                "pr_options": L.pr_options, "pr_stats": L.pr_stats,
                "pr_server_options": L.pr_server_options, "pr_request_info": L.pr_request_info,
-               "pr_fno_config": L.pr_fno_config}
+               "pr_fno_config": L.pr_fno_config, "pr_fno_file_info": L.pr_fno_file_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){']
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} %zu\\n", sizeof({sname}));')

@@ -251,6 +251,40 @@ def test_finite_termination_bitwise_mixed_fused_steps(pr, monkeypatch, fp32):
     s.close()
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_finite_termination_bitwise_bench_shape(pr, seed):
+    """The at-scale workload itself (513^2 FP32 increments, N = 64, numerical G on
+    the compiled-in 129^2 chain, sweeps over 64 slices on other row chunks than
+    serial F's): with tol = 0 the iteration runs to K = N and equals serial F
+    bitwise (seed 0 differed in the last bits while multiply-adds could fuse
+    across statements)."""
+    inst = plain_at_scale(seed).replace(tol=0.0)
+    say("finite termination bench shape", seed)
+    s = pr.Solver(inst)
+    ser = host(s.serial_fine().value)
+    res = s.solve()
+    assert res.iters == inst.n_slices
+    assert np.array_equal(host(res.value), ser)
+    s.close()
+
+
+def test_bench_shape_chain_vs_oracle(pr):
+    """513^2 / 129^2 FP32 (the compiled-in LDS chain) over Parareal iterations
+    k = 1, 2 against the oracle's Parareal, 4 slices of the at-scale length."""
+    inst = plain_at_scale(0).replace(n_slices=4, T=4.0 / 64, tol=0.0)
+    mf, mg, _, _ = pr.plan(inst)
+    say("bench shape chain vs oracle", mf, mg)
+    for k in (1, 2):
+        s = pr.Solver(inst, max_iters=k)
+        res = s.solve()
+        U, K, inc = oracle.parareal_bs(oproblem(inst), oproblem(inst, 129), 4, inst.T, mf, mg,
+                                       max_iters=k, tol=0.0)
+        assert res.iters == K == k
+        assert rel_max(host(res.value), U) <= FP32_TOL
+        assert np.allclose(res.increments, inc, rtol=1e-3)
+        s.close()
+
+
 @pytest.mark.parametrize("fp32", [False, True])
 def test_G_equal_F_one_iteration(pr, fp32):
     inst = plain_fp64(EXCHANGE).replace(fp32=fp32)
