@@ -32,6 +32,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s + p99 latency at err≤1e-5 vs serial F; stencil HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
+# FP32 operations of one interior point-step of the increment-form update
+# d+ = d + dt (Lb + L d): second differences 3 + 3, four-corner difference 3,
+# first differences 1 + 1, five coefficient products and the reaction 6 with 5
+# additions, then + Lb, * dt, + d.
+FLOPS_PER_POINT_STEP = 25
 SEEDS = list(range(8))
 
 
@@ -60,6 +65,22 @@ def measured_traffic_per_point_step(name="k_fine_tb_513x513x64_fp32.md"):
         if line.startswith("traffic_bytes_per_point_step:"):
             return float(line.split(":", 1)[1])
     return None
+
+
+def golden_oracle(name):
+    """A stored FP64 oracle solution (tests/golden/, written by a script that
+    calls only the oracle), or None when it has not been generated."""
+    import numpy as np
+    f = os.path.join(ROOT, "tests", "golden", name)
+    return np.load(f) if os.path.exists(f) else None
+
+
+def rel_err_sub(value, ref, every):
+    """Relative max-norm error of a device grid, subsampled every `every` nodes,
+    against a stored oracle subsample."""
+    import numpy as np
+    v = value.detach().cpu().numpy()[::every, ::every]
+    return float(np.abs(v - ref).max() / np.abs(ref).max())
 
 
 def nearest_rank(xs, p):
@@ -97,8 +118,12 @@ def main():
                     help="run only the training part of the neural coarse propagator leg")
     ap.add_argument("--largest-solve", action="store_true",
                     help="run only the 2049^2, 256-slice solve (LOD G) against serial F")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the 2049^2, 256-slice solve leg")
     ap.add_argument("--largest-share-only", action="store_true",
                     help="run only the 2049^2 x 32-slice step-kernel leg and print its JSON")
+    ap.add_argument("--step-probe", default=None,
+                    help="M,N: run only the step-kernel probe on an M^2 grid with N slices")
     ap.add_argument("--fno-train-s", type=float, default=30.0,
                     help="training budget of the neural coarse propagator leg (seconds)")
     args = ap.parse_args()
@@ -116,7 +141,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.largest_share_only:
+    if args.largest_share_only or args.step_probe:
         if args.copy_probe_mib:
             n = args.copy_probe_mib << 20
             src = torch.ones(n, dtype=torch.uint8, device=dev)
@@ -125,7 +150,11 @@ def main():
             dst.copy_(src)
             torch.cuda.synchronize()
             del src, dst
-        print(json.dumps(largest_share_leg(pr)), flush=True)
+        if args.step_probe:
+            M, N = (int(x) for x in args.step_probe.split(","))
+            print(json.dumps(step_probe(pr, M, N)), flush=True)
+        else:
+            print(json.dumps(largest_share_leg(pr)), flush=True)
         return
     if args.largest_solve:
         print(json.dumps(largest_solve(pr)), flush=True)
@@ -151,6 +180,7 @@ def main():
 
     # correctness outside the timed region: error vs the GPU serial fine solution
     errs, iters, serial_ms = {s: float("nan") for s in seeds}, {s: 0 for s in seeds}, {s: 0.0 for s in seeds}
+    errs_oracle, serial_errs_oracle = {}, {}
     serial_ref = {}
     for s in ([] if args.no_check else seeds):
         sv = solvers[s]
@@ -161,6 +191,10 @@ def main():
         res = sv.solve()
         iters[s] = res.iters
         errs[s] = float((res.value - ser_v).abs().max() / ser_v.abs().max())
+        ref = golden_oracle("c2_serial_f_seed%d.npy" % s)
+        if ref is not None:
+            errs_oracle[s] = rel_err_sub(res.value, ref, 4)
+            serial_errs_oracle[s] = rel_err_sub(ser_v, ref, 4)
 
     for w in range(args.warmup):
         solvers[seeds[w % len(seeds)]].solve()
@@ -214,6 +248,11 @@ def main():
         "p50_ms": round(nearest_rank(lat, 50), 3),
         "p99_ms": round(nearest_rank(lat, 99), 3),
         "max_err_vs_serial_f": None if args.no_check else max(errs.values()),
+        "max_err_vs_oracle": max(errs_oracle.values()) if errs_oracle else None,
+        "serial_f_max_err_vs_oracle": (max(serial_errs_oracle.values())
+                                       if serial_errs_oracle else None),
+        "oracle_reference": "FP64 oracle serial F of each seed on every 4th node (129^2 of "
+                            "513^2), stored by tests/golden/make_bench_oracle.py",
         "iters": [iters[s] for s in seeds],
         "serial_f_ms": [round(serial_ms[s], 2) for s in seeds],
         "parareal_ms": [round(x, 2) for x in lat[: len(seeds)]],
@@ -236,10 +275,12 @@ def main():
         out["graph"] = graph_leg(pr)
         if not args.no_fno:
             out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
+        if not args.no_largest:
+            out["largest_solve"] = largest_solve(pr)
     if args.max_iters:
         out["note"] = "iterations capped at %d (counter run, not a bench line)" % args.max_iters
     if not args.no_cpu_baseline and not args.no_check:
-        out["cpu_baseline"] = run_cpu_baseline(insts[0], iters[seeds[0]])
+        out["cpu_baseline"] = run_cpu_baseline(insts, iters[seeds[0]])
     print(json.dumps(out), flush=True)
 
 
@@ -288,6 +329,9 @@ def largest_solve(pr):
     t_par = time.perf_counter() - t
     err = float((r.value - ref).abs().max() / ref.abs().max())
     st = r.stats
+    ora = golden_oracle("c5_serial_f_257.npy")
+    ser_err_oracle = None if ora is None else rel_err_sub(ref, ora, 8)
+    par_err_oracle = None if ora is None else rel_err_sub(r.value, ora, 8)
     # the same solve with each iteration captured once as a hipGraph and replayed
     sg = pr.Solver(inst, coarse_kind=pr.PR_G_LOD, flags=pr.PR_FLAG_GRAPH)
     t = time.perf_counter()
@@ -303,6 +347,9 @@ def largest_solve(pr):
            "parareal_s": round(t_par, 2), "iters": r.iters, "err_vs_serial_f": err,
            "graph_parareal_s": round(t_graph, 2), "graph_iters": iters_graph,
            "graph_err_vs_serial_f": err_graph,
+           "serial_f_err_vs_oracle": ser_err_oracle, "parareal_err_vs_oracle": par_err_oracle,
+           "oracle_reference": "FP64 oracle serial F at 2049^2 on every 8th node (257^2), "
+                               "stored by tests/golden/make_bench_oracle.py",
            "increments": [float("%.3g" % x) for x in r.increments],
            "step_kernel_gbs": round(st["timed_step_bytes"] / (st["t_step_kernels_ms"] * 1e-3) / 1e9, 1),
            "phase_ms": {"fine": round(st["t_fine_ms"], 1),
@@ -363,29 +410,38 @@ def graph_leg(pr, reps=5):
     return res
 
 
-def largest_share_leg(pr):
-    """The step kernel at the shape one GPU would hold of the largest problem:
-    2049^2 grid, 32 of its 256 slices (slice length 2/256, 7207 explicit steps per
-    slice at 0.9 of the bound), one Parareal iteration (the fine sweep over all 32
-    slices; the same-grid implicit G).  Achieved = 12 B per interior point-step
-    over the HIP-event time of the step launches."""
+def step_probe(pr, M=2049, n_slices=32):
+    """The step kernel alone at one shape: an M^2 grid with the parameters of the
+    largest single solve and slices of its length (2/256, so 7207 explicit steps
+    per slice at 2049^2 and 1802 at 1025^2), one Parareal iteration (the fine
+    sweep over all slices; the same-grid implicit G), solved twice (warm-up,
+    then measured).  Reports the HIP-event time of the step launches as point-
+    steps/s, as 12 B per point-step (the unfused algorithmic bytes) and as the
+    25 FP32 operations per point-step of the update."""
     import torch
     from synthetic import largest_single
-    inst = largest_single().replace(n_slices=32, T=2.0 / 8, coarse_steps_per_slice=4)
+    inst = largest_single().replace(M=M, n_slices=n_slices, T=2.0 * n_slices / 256,
+                                    coarse_steps_per_slice=4)
     sv = pr.Solver(inst, coarse_kind=pr.PR_G_LOD, flags=pr.PR_FLAG_TIME_STEPS, max_iters=1)
     sv.solve()
     torch.cuda.synchronize()
     r = sv.solve()
     st = r.stats
     sv.close()
-    ach = st["timed_step_bytes"] / (st["t_step_kernels_ms"] * 1e-3) / 1e9
-    return {"workload": "2049^2 FP32 increment form, 32 slices of dT = 2/256 (one of 8 GPUs' "
-                        "share of the 256-slice problem), %d explicit steps per slice, one "
-                        "fine sweep" % st["fine_steps"],
-            "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+    pts = st["timed_step_bytes"] / 12.0 / (st["t_step_kernels_ms"] * 1e-3)
+    return {"workload": "%d^2 FP32 increment form, %d slices of dT = 2/256, %d explicit steps "
+                        "per slice, one fine sweep" % (M, n_slices, st["fine_steps"]),
+            "point_steps_per_s": round(pts, 1),
+            "effective_gbs": round(pts * 12.0 / 1e9, 1),
+            "achieved_tflops": round(pts * FLOPS_PER_POINT_STEP / 1e12, 3),
             "step_launches": st["fine_step_launches"], "timed_launches": st["timed_step_launches"],
             "avg_launch_us": round(st["t_step_kernels_ms"] * 1e3 / max(1, st["timed_step_launches"]), 2),
-            "point_steps_per_s": round(st["timed_step_bytes"] / 12.0 / (st["t_step_kernels_ms"] * 1e-3), 1)}
+            "point_steps_per_launch": round(st["timed_step_bytes"] / 12.0 / max(1, st["timed_step_launches"]))}
+
+
+def largest_share_leg(pr):
+    """One GPU's share of the largest solve: 2049^2, 32 of its 256 slices."""
+    return step_probe(pr, 2049, 32)
 
 
 def fno_flops_per_sample():
@@ -501,17 +557,35 @@ def serving_leg(pr, count=120, seed=11, sides=(129, 257)):
     return out
 
 
-def run_cpu_baseline(inst, K_gpu):
-    """FP64 oracle Parareal on the host cores, bounded sample: t_init (max_iters=0)
-    and t_init + t_iter (max_iters=1) on the seed-0 instance at 513^2; a full solve
-    is scaled as t_init + K * t_iter with the GPU's K for that instance."""
+def run_cpu_baseline(insts, K_gpu):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload.
+
+    Measured: the oracle's complete serial F of the seed-3 instance (the
+    cheapest of the eight: 64 slices x 283 explicit steps on 513^2) with every
+    host thread on the rows; the workload's solves/s follows by scaling that
+    point-step rate to the mean serial-F point-steps of the eight instances (the
+    exact answer the GPU's Parareal solves approximate to 1e-5).  Also reported:
+    the oracle's own Parareal on seed 0 (initial sweep + one iteration
+    measured, a K-iteration solve extrapolated as init + K * iter)."""
     import oracle
     from paper_2404_02521_amd.parareal import plan
+
+    def prob(inst, M=None):
+        return oracle.Problem(M=M or inst.M, sigma1=inst.sigma1, sigma2=inst.sigma2,
+                              rho=inst.rho, r=inst.r, payoff_kind=inst.payoff, w1=inst.w1,
+                              w2=inst.w2, strike=inst.strike)
+
+    sample = insts[3] if len(insts) > 3 else insts[0]
+    mf_s = plan(sample)[0]
+    t = time.perf_counter()
+    oracle.serial_fine(prob(sample), sample.n_slices, sample.T, mf_s)
+    t_ser = time.perf_counter() - t
+    pts = sample.n_slices * mf_s * (sample.M - 2) ** 2
+    rate = pts / t_ser
+    mean_pts = sum(i.n_slices * plan(i)[0] * (i.M - 2) ** 2 for i in insts) / len(insts)
+    inst = insts[0]
     mf, mg, _, _ = plan(inst)
-    kw = dict(sigma1=inst.sigma1, sigma2=inst.sigma2, rho=inst.rho, r=inst.r,
-              payoff_kind=inst.payoff, w1=inst.w1, w2=inst.w2, strike=inst.strike)
-    pf = oracle.Problem(M=inst.M, **kw)
-    pc = oracle.Problem(M=inst.coarse_M, **kw)
+    pf, pc = prob(inst), prob(inst, inst.coarse_M)
     t = time.perf_counter()
     oracle.parareal_bs(pf, pc, inst.n_slices, inst.T, mf, mg, max_iters=0, tol=0.0)
     t_init = time.perf_counter() - t
@@ -519,13 +593,20 @@ def run_cpu_baseline(inst, K_gpu):
     oracle.parareal_bs(pf, pc, inst.n_slices, inst.T, mf, mg, max_iters=1, tol=0.0)
     t_one = time.perf_counter() - t
     t_iter = max(t_one - t_init, 1e-9)
-    t_solve = t_init + K_gpu * t_iter
-    return {"value": round(1.0 / t_solve, 6), "unit": "solves/s",
+    return {"value": round(rate / mean_pts, 6), "unit": "solves/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "FP64 oracle Parareal, seed-0 513^2 instance (N=64, %d fine steps/slice): "
-                      "init sweep %.2fs + one iteration %.2fs measured, full solve scaled as "
-                      "init + K*iter with K=%d; host %s" % (mf, t_init, t_iter, K_gpu,
-                                                            host_cpu_model())}
+            "sample": "FP64 oracle serial F, complete solve of the seed-3 513^2 instance "
+                      "(64 slices x %d steps, %.3g point-steps) in %.2f s measured on %d host "
+                      "threads (rows in parallel), %.3g point-steps/s; scaled to the mean "
+                      "serial-F work of seeds 0-7 (%.3g point-steps); host %s"
+                      % (mf_s, pts, t_ser, oracle.num_threads(), rate, mean_pts,
+                         host_cpu_model()),
+            "measured_s": round(t_ser, 3), "point_steps_per_s": round(rate, 1),
+            "parareal_extrapolated": {
+                "solves_per_s": round(1.0 / (t_init + K_gpu * t_iter), 6),
+                "how": "oracle Parareal on seed 0 (OpenMP over slices): init %.2f s + one "
+                       "iteration %.2f s measured, a solve taken as init + K*iter with the "
+                       "GPU's K=%d (not measured end to end)" % (t_init, t_iter, K_gpu)}}
 
 
 if __name__ == "__main__":

@@ -5,7 +5,7 @@
  * TEST INFRASTRUCTURE ONLY.  This file is the oracle the HIP path is checked
  * against.  It shares no code, header, table or helper with the product
  * library; only tests, the smoke check and the CPU-baseline leg of the bench
- * may load it.  It is compiled with -O2 -ffp-contract=off so every operation
+ * may load it.  It is compiled with -O3 -ffp-contract=off (no fast-math) so every operation
  * below is one IEEE double rounding in the order written.
  *
  * What it computes (paper: "Space-time parallel scaling of Parareal with a
@@ -171,6 +171,11 @@ void orc_apply_operator(const orc_problem* p, const double* u, double* Lu)
 void orc_euler_step(const orc_problem* p, double dt, const double* u, double* out)
 {
     const int M = p->M;
+    /* rows in parallel (each node is the same independent expression; inside
+     * the slice-parallel Parareal driver this region runs on one thread) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) if (M > 64)
+#endif
     for (int i = 1; i < M - 1; ++i)
         for (int j = 1; j < M - 1; ++j) {
             size_t k = (size_t)i * M + j;

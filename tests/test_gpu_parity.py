@@ -139,7 +139,7 @@ def test_exact_bc_fp64(pr):
 def test_discounted_payoff_bc(pr, fp32):
     """The literal discounted-payoff ring (e^{-r tau} times the payoff) through
     serial F and two Parareal iterations, against the oracle."""
-    inst = plain_fp64(BASKET).replace(M=131, coarse_M=33, fine_steps_per_slice=0,
+    inst = plain_fp64(BASKET).replace(M=129, coarse_M=33, fine_steps_per_slice=0,
                                       coarse_steps_per_slice=0, T=0.25, n_slices=4, tol=0.0,
                                       fp32=fp32)
     mf, mg, _, _ = pr.plan(inst)
