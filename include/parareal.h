@@ -214,6 +214,28 @@ pr_status parareal_apply(pr_solver* s, int32_t op, int32_t slice, const double* 
 
 pr_status parareal_destroy(pr_solver* s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * solve, as parareal_create + parareal_solve + parareal_destroy, on a workspace
+ * that is a static device array of PR_STATIC_SCRATCH_BYTES inside the library
+ * (one copy per GPU, held until the process ends).  It calls no hipMalloc,
+ * hipFree or other allocating routine and creates no event, stream or graph;
+ * PR_FLAG_TIME_STEPS and PR_FLAG_GRAPH are ignored (phase timings stay 0).
+ * The stream must belong to the current device; v_out (device, n*n doubles)
+ * and stats (host, may be NULL) as in parareal_solve, and the same kernels run
+ * with the same launch geometry, so the result equals parareal_solve's bitwise.
+ * Errors: PR_ENOMEM when the problem's workspace (parareal_workspace_bytes)
+ * exceeds PR_STATIC_SCRATCH_BYTES; PR_EINVAL for PR_G_FNO (it needs an attached
+ * operator) and for the argument errors of parareal_create; PR_EDEVICE when the
+ * scratch's device address cannot be obtained.  Every call on one GPU uses that
+ * GPU's one array and keeps its contents after returning: calls that overlap on
+ * one GPU (other threads, other streams) race and must be serialised by the
+ * caller. */
+#define PR_STATIC_SCRATCH_BYTES (64ull << 20)
+pr_status parareal_solve_static(const pr_grid* grid, const pr_model* model,
+                                const pr_payoff* payoff, const pr_options* opt, void* hip_stream,
+                                double* v_out, pr_stats* stats);
+
 /* PR_G_FNO solvers: attach the operator (borrowed, not owned; it must outlive
  * the solver's use of it and is used on the solver's stream, one solve at a
  * time).  PR_EINVAL for solvers of another coarse kind. */

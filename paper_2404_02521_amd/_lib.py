@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libparareal.so")
 
 PR_MAX_SLICES = 1024
+PR_STATIC_SCRATCH_BYTES = 64 << 20
 
 PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_ENOTCONV, PR_ENONFINITE, PR_EMODEL = range(8)
 PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE = 0, 1
@@ -98,6 +99,9 @@ SIGNATURES = [
     ("parareal_serial_fine", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(pr_stats)]),
     ("parareal_apply", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     ("parareal_destroy", C.c_int, [C.c_void_p]),
+    ("parareal_solve_static", C.c_int, [C.POINTER(pr_grid), C.POINTER(pr_model),
+                                        C.POINTER(pr_payoff), C.POINTER(pr_options), C.c_void_p,
+                                        C.c_void_p, C.POINTER(pr_stats)]),
     ("parareal_attach_fno", C.c_int, [C.c_void_p, C.c_void_p]),
     ("parareal_fno_pair", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                      C.c_void_p]),

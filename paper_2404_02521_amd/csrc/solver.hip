@@ -17,6 +17,7 @@
 #include <new>
 #include <string>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/parareal.h"
@@ -857,11 +858,18 @@ uint64_t parareal_workspace_bytes(const pr_grid* grid, const pr_options* opt) {
     return layout(grid, opt).total;
 }
 
-pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_payoff* payoff,
-                          const pr_options* opt, void* device_workspace, uint64_t workspace_bytes,
-                          void* hip_stream, pr_solver** out) {
-    if (!out) return PR_EINVAL;
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Validates the arguments and fills a solver bound to device_workspace (no GPU
+// call before validation has passed).  with_runtime_objects: create the
+// timing events, the capture stream and the step-event pairs (parareal_create);
+// without them (the static-scratch entry point) the solver creates no runtime
+// object and PR_FLAG_TIME_STEPS / PR_FLAG_GRAPH are ignored.
+pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
+                       const pr_payoff* payoff, const pr_options* opt, void* device_workspace,
+                       uint64_t workspace_bytes, void* hip_stream, bool with_runtime_objects) {
     if (!grid || !model || !payoff || !opt) return PR_EINVAL;
     std::string why;
     if (!valid_basic(grid, opt, &why)) return PR_EINVAL;
@@ -880,8 +888,6 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     if (!device_workspace || workspace_bytes < L.total) return PR_ENOMEM;
     if (reinterpret_cast<uintptr_t>(device_workspace) % kAlign) return PR_EINVAL;
 
-    pr_solver* s = new (std::nothrow) pr_solver();
-    if (!s) return PR_ENOMEM;
     s->grid = *grid;
     s->model = *model;
     s->pay = *payoff;
@@ -929,17 +935,9 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
     if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_TIME_EVERY")) s->ev_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_MINROWS")) s->min_rows = std::max(1, std::atoi(e));
-    if (!s->fineg) {
-        hipError_t e = chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0));
-        if (e != hipSuccess) {
-            delete s;
-            return PR_EDEVICE;
-        }
-    }
-    if ((s->lod || s->fnog) && lod_set_lds(s->fg.nin) != hipSuccess) {
-        delete s;
+    if (!s->fineg && chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0)) != hipSuccess)
         return PR_EDEVICE;
-    }
+    if ((s->lod || s->fnog) && lod_set_lds(s->fg.nin) != hipSuccess) return PR_EDEVICE;
     if (s->fnog) {
         std::vector<double> R, P;
         sine_transfer_matrices(s->fg.nin, R, P);
@@ -949,21 +947,15 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
             e = hipMemcpyAsync(s->at<double>(L.Sp), P.data(), P.size() * 8, hipMemcpyHostToDevice,
                                s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        if (e != hipSuccess) {
-            delete s;
-            return PR_EDEVICE;
-        }
+        if (e != hipSuccess) return PR_EDEVICE;
     }
+    if (!with_runtime_objects) return PR_OK;
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     s->events = ok;
     s->graph = (opt->flags & PR_FLAG_GRAPH) != 0;
-    if (s->graph && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        for (auto& e : s->ev)
-            if (e) (void)hipEventDestroy(e);
-        delete s;
+    if (s->graph && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return PR_EDEVICE;
-    }
     if ((opt->flags & PR_FLAG_TIME_STEPS) && !s->graph) {
         s->step_ev.resize(2 * (size_t)mf, nullptr);
         for (auto& e : s->step_ev)
@@ -977,8 +969,102 @@ pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_p
             s->step_ev.clear();
         }
     }
+    return PR_OK;
+}
+
+void release_runtime_objects(pr_solver* s) {
+    for (auto& e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : s->step_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->graph_defs) (void)hipGraphDestroy(kv.second);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of parareal_solve_static: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel or a
+// copy (on the host the name is a stand-in, not a device address); it uses
+// the per-device address hipGetSymbolAddress returns.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kStaticScratchBytes = PR_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up once per device, with
+// that device current).
+pr_status static_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return PR_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PR_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pr_status parareal_create(const pr_grid* grid, const pr_model* model, const pr_payoff* payoff,
+                          const pr_options* opt, void* device_workspace, uint64_t workspace_bytes,
+                          void* hip_stream, pr_solver** out) {
+    if (!out) return PR_EINVAL;
+    *out = nullptr;
+    pr_solver* s = new (std::nothrow) pr_solver();
+    if (!s) return PR_ENOMEM;
+    const pr_status st = setup_solver(s, grid, model, payoff, opt, device_workspace,
+                                      workspace_bytes, hip_stream, true);
+    if (st != PR_OK) {
+        release_runtime_objects(s);
+        delete s;
+        return st;
+    }
     *out = s;
     return PR_OK;
+}
+
+pr_status parareal_solve_static(const pr_grid* grid, const pr_model* model,
+                                const pr_payoff* payoff, const pr_options* opt, void* hip_stream,
+                                double* v_out, pr_stats* st) {
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (!grid || !model || !payoff || !opt || !v_out) return PR_EINVAL;
+    if (opt->coarse_kind == PR_G_FNO) return PR_EINVAL;   // needs an attached operator
+    if (!valid_basic(grid, opt, nullptr)) return PR_EINVAL;
+    if (layout(grid, opt).total > kStaticScratchBytes) return PR_ENOMEM;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PR_EDEVICE;
+    void* ws = nullptr;
+    pr_status r = static_scratch(dev, &ws);
+    if (r != PR_OK) return r;
+    auto t0 = std::chrono::steady_clock::now();
+    pr_solver s;   // on the stack: no runtime objects, no device memory
+    pr_options o = *opt;
+    o.flags &= ~(PR_FLAG_TIME_STEPS | PR_FLAG_GRAPH);
+    r = setup_solver(&s, grid, model, payoff, &o, ws, kStaticScratchBytes, hip_stream, false);
+    if (r == PR_OK) {
+        try {
+            r = do_solve(&s, v_out, st);
+        } catch (...) {
+            r = PR_EDEVICE;
+        }
+    }
+    if (st) {
+        st->status = r;
+        st->fine_steps = s.mF;
+        st->coarse_steps = s.mG;
+        st->workspace_bytes = s.L.total;
+        st->t_total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return r;
 }
 
 pr_status parareal_solve(pr_solver* s, double* v_out, pr_stats* st) {
@@ -1168,13 +1254,7 @@ pr_status parareal_fno_pairs(pr_solver* s, int32_t base, float* pairs_out) {
 
 pr_status parareal_destroy(pr_solver* s) {
     if (!s) return PR_EINVAL;
-    for (auto& e : s->ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto& e : s->step_ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto& kv : s->graph_defs) (void)hipGraphDestroy(kv.second);
-    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    release_runtime_objects(s);
     delete s;
     return PR_OK;
 }

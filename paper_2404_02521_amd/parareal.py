@@ -58,6 +58,28 @@ def plan(inst, coarse_kind: int = L.PR_G_NUMERICAL):
     return mf.value, mc.value, df.value, dc.value
 
 
+def solve_static(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
+                 bc_kind: int = L.PR_BC_FORWARD_INTRINSIC, device=None, stream=None,
+                 out=None) -> SolveResult:
+    """One solve through parareal_solve_static: the library's static device
+    scratch is the workspace, so nothing is allocated but the output tensor
+    (pass ``out`` to allocate nothing at all)."""
+    import torch
+    device = torch.device(device or "cuda")
+    g, m, p, o = make_structs(inst, coarse_kind, max_iters, bc_kind, 0)
+    if out is None:
+        out = torch.empty((inst.M, inst.M), dtype=torch.float64, device=device)
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.shape == (inst.M, inst.M)
+    stream = stream if stream is not None else torch.cuda.current_stream(device)
+    st = L.pr_stats()
+    status = L.lib().parareal_solve_static(C.byref(g), C.byref(m), C.byref(p), C.byref(o),
+                                           C.c_void_p(stream.cuda_stream),
+                                           C.c_void_p(out.data_ptr()), C.byref(st))
+    if status not in (L.PR_OK, L.PR_ENOTCONV):
+        L.check(status, "parareal_solve_static")
+    return SolveResult(out, st.iters, list(st.increments[:st.iters]), status, _stats_dict(st))
+
+
 class Solver:
     """One solver bound to a workspace tensor and the current stream."""
 
