@@ -37,34 +37,50 @@ HBM_PEAK_GBS = 8000.0
 # first differences 1 + 1, five coefficient products and the reaction 6 with 5
 # additions, then + Lb, * dt, + d.
 FLOPS_PER_POINT_STEP = 25
+# MI355X FP32 vector peak as published (it counts packed FP32, two FMAs per lane
+# per cycle), and the single-issue figure 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# x 2.4 GHz that applies to code built without packed FP32, as this library is
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_NONPACKED_TFLOPS = 78.6
 SEEDS = list(range(8))
 
 
+KERNEL_SOURCES = ("device.hpp", "kernels.hip")
+
+
 def kernel_source_hash() -> str:
-    """First 16 hex digits of sha256 over the step kernel's source and the
-    solver that sets its launch geometry (kernels.hip, then solver.hip)."""
+    """First 16 hex digits of sha256 over the step kernel's sources (device.hpp,
+    then kernels.hip)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "solver.hip"):
+    for name in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_2404_02521_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic_per_point_step(name="k_fine_tb_513x513x64_fp32.md"):
-    """HBM bytes per interior point-step of the step kernel on the headline
-    workload, from its committed rocprofv3 counter summary (FETCH_SIZE x2 +
-    WRITE_SIZE x1, copy-calibrated), or None when that summary was taken on
-    another version of the kernel source."""
+def profile_figures(name):
+    """`key: value` figures of a committed rocprofv3 summary under profiles/, or
+    {} when the summary is missing or was taken on another kernel source."""
     f = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(f):
-        return None
+        return {}
     txt = open(f).read()
     if "kernel_source_sha256: " + kernel_source_hash() not in txt:
-        return None
+        return {}
+    out = {}
     for line in txt.splitlines():
-        if line.startswith("traffic_bytes_per_point_step:"):
-            return float(line.split(":", 1)[1])
-    return None
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            try:
+                out[k.strip()] = float(v)
+            except ValueError:
+                pass
+    return out
+
+
+def progress(msg):
+    """One progress line on stderr (stdout carries only the JSON result)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def golden_oracle(name):
@@ -196,6 +212,7 @@ def main():
             errs_oracle[s] = rel_err_sub(res.value, ref, 4)
             serial_errs_oracle[s] = rel_err_sub(ser_v, ref, 4)
 
+    progress("correctness pass done")
     for w in range(args.warmup):
         solvers[seeds[w % len(seeds)]].solve()
     torch.cuda.synchronize()
@@ -220,14 +237,18 @@ def main():
         corr_ms += st["t_correct_ms"]
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    progress("timed region done: %.2f solves/s" % (args.steps / total))
 
     value = args.steps / total
-    achieved = steps_bytes / (steps_ms * 1e-3) / 1e9 if steps_ms > 0 else 0.0
-    tpp = measured_traffic_per_point_step()
-    # algorithmic bytes are 12 B per point-step, so the average launch's point-steps
-    # are bytes_per_launch / 12
-    traffic = None if tpp is None else round(tpp * steps_bytes / 12.0 / max(1, steps_launch))
+    # point-steps of the event-timed step launches (12 B algorithmic per point-step)
+    pts_per_s = steps_bytes / 12.0 / (steps_ms * 1e-3) if steps_ms > 0 else 0.0
+    achieved_tflops = pts_per_s * FLOPS_PER_POINT_STEP / 1e12
+    head = profile_figures("k_fine_tb_513x513x64_fp32.md")
+    share = profile_figures("k_fine_tb_2049x2049x32_fp32.md")
     avg_launch_us = steps_ms * 1e3 / max(1, steps_launch)
+    pts_per_launch = steps_bytes / 12.0 / max(1, steps_launch)
+    traffic = (round(head["hbm_bytes_per_point_step"] * pts_per_launch)
+               if "hbm_bytes_per_point_step" in head else None)
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -258,25 +279,49 @@ def main():
         "parareal_ms": [round(x, 2) for x in lat[: len(seeds)]],
         "phase_ms": {"fine_sweeps": round(fine_ms, 2), "coarse_chain": round(chain_ms, 2),
                      "correction": round(corr_ms, 2), "step_kernels_timed": round(steps_ms, 2)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel_source_sha256": kernel_source_hash(),
-                     "kernel": "k_fine_tb<MODE_INCR, S=6> (FP32 increment form, 6 explicit steps per launch "
-                               "in registers, 12 B per point-step algorithmic)",
-                     "avg_launch_us": round(avg_launch_us, 3),
-                     "bytes_per_launch": round(steps_bytes / max(1, steps_launch)),
-                     "timed_launches": steps_launch, "all_launches": all_launch,
-                     "all_bytes_per_launch": round(all_bytes / max(1, all_launch))},
+        "roofline": {
+            "bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "kernel": "k_fine_tb<MODE_INCR, S=6> (FP32 increment form, 6 explicit steps per launch "
+                      "in registers, neighbour weights with dt folded in)",
+            "why_alu": "rocprofv3 SQ counters: the kernel issues VALU instructions at the chip's "
+                       "VALU issue rate while its HBM traffic stays well below peak (profiles/)",
+            "flops_per_point_step": FLOPS_PER_POINT_STEP,
+            "point_steps_per_s": round(pts_per_s, 1),
+            "peak_without_packed_fp32_tflops": FP32_VECTOR_NONPACKED_TFLOPS,
+            "frac_without_packed_fp32": round(achieved_tflops / FP32_VECTOR_NONPACKED_TFLOPS, 4),
+            "effective_gbs": round(pts_per_s * 12.0 / 1e9, 1),
+            "valu_instr_per_point_step": head.get("valu_instr_per_point_step"),
+            "valu_issue_frac": head.get("valu_issue_frac"),
+            "hbm_gbs": (round(head["hbm_bytes_per_point_step"] * pts_per_s / 1e9, 1)
+                        if "hbm_bytes_per_point_step" in head else None),
+            "hbm_frac": (round(head["hbm_bytes_per_point_step"] * pts_per_s / 1e9 / HBM_PEAK_GBS, 4)
+                         if "hbm_bytes_per_point_step" in head else None),
+            "above_cache_2049x32": {k: share.get(k) for k in (
+                "point_steps_per_s", "hbm_bytes_per_point_step", "hbm_gbs", "hbm_frac",
+                "valu_instr_per_point_step", "valu_issue_frac", "achieved_tflops")},
+            "kernel_source_sha256": kernel_source_hash(),
+            "avg_launch_us": round(avg_launch_us, 3),
+            "point_steps_per_launch": round(pts_per_launch),
+            "timed_launches": steps_launch, "all_launches": all_launch},
     }
     if not args.no_check:
         out["lod_coarse"] = lod_leg(pr, insts, seeds, serial_ref)
+        progress("lod leg done")
         out["serving"] = serving_leg(pr)
+        progress("serving leg done")
         out["largest_share"] = largest_share_leg(pr)
+        out["above_cache_1025x64"] = step_probe(pr, 1025, 64)
+        progress("step-kernel probes done")
         out["graph"] = graph_leg(pr)
+        progress("graph leg done")
         if not args.no_fno:
             out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
+            progress("fno leg done")
         if not args.no_largest:
             out["largest_solve"] = largest_solve(pr)
+            progress("largest solve done")
     if args.max_iters:
         out["note"] = "iterations capped at %d (counter run, not a bench line)" % args.max_iters
     if not args.no_cpu_baseline and not args.no_check:

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define PR_ABI_VERSION 1
+#define PR_ABI_VERSION 2
 #define PR_MAX_SLICES 1024
 
 typedef struct pr_solver pr_solver; /* opaque */
@@ -104,6 +104,16 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
  * PR_ENONFINITE, as for the other propagators). */
 #define PR_FLAG_NO_FALLBACK 4u
 
+/* Time stepping of the fine propagator F.  PR_FINE_EXPLICIT: explicit Euler
+ * (the planner keeps dt below the stability bound).  PR_FINE_IMPLICIT: implicit
+ * Euler exactly as Eq. (fd) (Sec. 3.2): every step solves (I - dt L_h) u+ = u on
+ * the interior with the ring of u+ at the new time, by Jacobi-preconditioned
+ * BiCGStab on the GPU (matrix-free, all slices of a sweep together) to the
+ * relative residual krylov_tol; it needs PR_FP64 and fine_steps >= 1, and is not
+ * available with PR_FLAG_GRAPH or through the server (the solver polls the
+ * iteration on the host). */
+enum { PR_FINE_EXPLICIT = 0, PR_FINE_IMPLICIT = 1 };
+
 /* Arithmetic of the fine and numerical coarse propagators. */
 enum { PR_FP64 = 0, /* everything in FP64 */
        PR_FP32 = 1  /* FP32 increments over an FP64 slice base; correction and norm FP64 */ };
@@ -141,7 +151,10 @@ typedef struct {
     int32_t coarse_steps;   /* coarse steps per slice; 0 => planned from cfl (PR_G_LOD: 2) */
     double cfl;             /* planned dt = dT / ceil(dT / (cfl * dt_stable)); (0, 1] */
     uint32_t flags;         /* PR_FLAG_* bits */
-    int32_t pad_;
+    int32_t fine_scheme;    /* PR_FINE_* */
+    double krylov_tol;      /* PR_FINE_IMPLICIT: relative residual ||r|| / ||b||; 0 => 1e-12 */
+    int32_t krylov_max_iters; /* PR_FINE_IMPLICIT: BiCGStab iterations per step; 0 => 1000 */
+    int32_t pad2_;
 } pr_options;
 
 typedef struct {
@@ -168,6 +181,10 @@ typedef struct {
     int32_t pad_;
     int64_t timed_step_launches; /* step launches bracketed by events (PR_FLAG_TIME_STEPS) */
     double timed_step_bytes;     /* their algorithmic bytes (t_step_kernels_ms covers them) */
+    int64_t krylov_iters;        /* PR_FINE_IMPLICIT: BiCGStab iterations summed over steps
+                                    (a step runs until its last slice converges) */
+    int32_t krylov_max_step;     /* most iterations one step took */
+    int32_t krylov_unconverged;  /* slice-steps stopped at krylov_max_iters or by a breakdown */
 } pr_stats;
 
 /* Explicit-Euler stability bound and the planned step counts (host only, no

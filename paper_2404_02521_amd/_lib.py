@@ -20,6 +20,7 @@ PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE = 0, 1
 PR_BC_FORWARD_INTRINSIC, PR_BC_DISCOUNTED_PAYOFF, PR_BC_EXACT = 0, 1, 2
 PR_G_NUMERICAL, PR_G_FNO, PR_G_FINE, PR_G_LOD = 0, 1, 2, 3
 PR_FP64, PR_FP32 = 0, 1
+PR_FINE_EXPLICIT, PR_FINE_IMPLICIT = 0, 1
 PR_OP_FINE, PR_OP_COARSE = 0, 1
 PR_FLAG_TIME_STEPS = 1
 PR_FLAG_GRAPH = 2
@@ -48,7 +49,8 @@ class pr_options(C.Structure):
     _fields_ = [("n_slices", C.c_int32), ("max_iters", C.c_int32), ("tol", C.c_double),
                 ("tol_relative", C.c_int32), ("precision", C.c_int32), ("fine_steps", C.c_int32),
                 ("coarse_kind", C.c_int32), ("coarse_n", C.c_int32), ("coarse_steps", C.c_int32),
-                ("cfl", C.c_double), ("flags", C.c_uint32), ("pad_", C.c_int32)]
+                ("cfl", C.c_double), ("flags", C.c_uint32), ("fine_scheme", C.c_int32),
+                ("krylov_tol", C.c_double), ("krylov_max_iters", C.c_int32), ("pad2_", C.c_int32)]
 
 
 class pr_stats(C.Structure):
@@ -61,7 +63,8 @@ class pr_stats(C.Structure):
                 ("fine_step_bytes", C.c_double), ("t_step_kernels_ms", C.c_double),
                 ("workspace_bytes", C.c_uint64), ("coarse_fallback", C.c_int32),
                 ("pad_", C.c_int32), ("timed_step_launches", C.c_int64),
-                ("timed_step_bytes", C.c_double)]
+                ("timed_step_bytes", C.c_double), ("krylov_iters", C.c_int64),
+                ("krylov_max_step", C.c_int32), ("krylov_unconverged", C.c_int32)]
 
 
 class pr_server_options(C.Structure):

@@ -56,23 +56,25 @@ __device__ inline double ring_value(const Bc& b, double x, double y, double tau,
 
 // Wavefront shifts through DPP (no LDS traffic): shr1 gives lane l the value
 // of lane l-1, shl1 the value of lane l+1.  Lanes whose source is outside the
-// wavefront receive 0 and are patched by the caller.
+// wavefront receive 0 (bound_ctrl: the hardware writes zero, so no old value
+// has to be materialised and the shift can become a DPP operand of the
+// instruction that consumes it); callers patch those lanes.
 __device__ inline float shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 __device__ inline float shl1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 __device__ inline double shr1(double v) {
     int2 p = *reinterpret_cast<int2*>(&v);
-    p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x138, 0xF, 0xF, false);
-    p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x138, 0xF, 0xF, false);
+    p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x138, 0xF, 0xF, true);
+    p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x138, 0xF, 0xF, true);
     return *reinterpret_cast<double*>(&p);
 }
 __device__ inline double shl1(double v) {
     int2 p = *reinterpret_cast<int2*>(&v);
-    p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x130, 0xF, 0xF, false);
-    p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x130, 0xF, 0xF, false);
+    p.x = __builtin_amdgcn_update_dpp(0, p.x, 0x130, 0xF, 0xF, true);
+    p.y = __builtin_amdgcn_update_dpp(0, p.y, 0x130, 0xF, 0xF, true);
     return *reinterpret_cast<double*>(&p);
 }
 

@@ -73,4 +73,38 @@ struct ChainArgs {
     const double* foldc;   // [slice][nc][nc]: F(U^k_n) at the coincident nodes
 };
 
+// Implicit-Euler fine steps by BiCGStab (krylov.hip).
+struct KrylovArgs {
+    Grid g;
+    Coef c;
+    Bc bc;
+    double dt;      // implicit step
+    double dT;      // slice length
+    int first;      // first slice index (absolute, for time)
+    int count;      // slices in the sweep
+    int step;       // step q of the slice: the new time is T_n + (q + 1) dt
+    int rows;       // interior rows per workgroup
+    int nblk;       // workgroups per slice (= partials per slice)
+    int it;         // BiCGStab iteration (selects the scalar slot and the p / v buffers)
+    double tol2;    // squared relative residual tolerance
+};
+
+// Per-slice scalars: two slots alternating by iteration parity, then flags.
+struct KScal {
+    double rho[2], alpha[2], omega[2];
+    double bb;         // (b, b)
+    double rr;         // (r, r) when the slice finished (or at the iteration cap)
+    int done;          // 1 once converged (or broke down)
+    int iters;         // iterations performed
+    int breakdown;     // 1 if a denominator vanished before convergence
+    int pad_;
+};
+
+struct KrylovBufs {
+    double *R, *RH, *P[2], *V[2], *S, *T;   // count slices each (interior layout)
+    double *partA, *partB, *partC;           // count * nblk (* 2) partial sums
+    KScal* sc;                               // count scalar records
+    int* ndone;                              // finished-slice counter (device)
+};
+
 }  // namespace pr

@@ -1,13 +1,13 @@
 // kernels.hip -- gfx950 kernels of the Parareal hot path.
 //
-//  k_fine_step   : one explicit Euler step of the centred 9-point operator of
-//                  Eq. (fd) (Sec. 3.2) over a batch of time slices.  Three
-//                  modes: FP64 state (u+ = u + dt L u), FP32 increment
-//                  (d+ = d + dt (Lb + L d) over an FP64 base b), and the FP32
-//                  preparation step that evaluates Lb = L b in FP64 and writes
-//                  the first increment dt*Lb.
+//  k_fine_prep   : the first explicit Euler step of the FP32 increment form
+//                  over a batch of time slices: evaluates L b of the centred
+//                  9-point operator of Eq. (fd) (Sec. 3.2) in FP64 for the FP64
+//                  slice base b and writes dt*L b (the stored term of every
+//                  later step, and the first increment).
 //  k_fine_tb     : S explicit steps of the same operator per launch
-//                  (temporal blocking in registers), the hot kernel of F.
+//                  (temporal blocking in registers), the hot kernel of F;
+//                  k_row_weights fills its per-row weight table.
 //  k_coarse_chain: the serial sweep of Eq. (parareal) (Sec. 3.1) restricted
 //                  to the coarse grid, one workgroup, coarse state in LDS (in
 //                  global memory when it does not fit).
@@ -27,7 +27,7 @@
 
 namespace pr {
 
-enum { MODE_DIRECT = 0, MODE_INCR = 1, MODE_PREP = 2 };
+enum { MODE_DIRECT = 0, MODE_INCR = 1 };
 enum { P_GEN = 0, P_MID = 1, P_FAST = 2 };   // row paths of the temporally blocked kernel
 
 // f(integral_constant<int, 0>) ... f(integral_constant<int, N-1>), unrolled.
@@ -40,17 +40,17 @@ __device__ __attribute__((always_inline)) inline void static_for(Fn&& f) {
 }
 
 // ---------------------------------------------------------------------------
-// Fine stencil step.  Each wavefront owns a strip of 64 consecutive interior
-// columns and a chunk of `rows` consecutive rows of one slice.  It walks down
-// the rows keeping rows i-1, i, i+1 in registers: every value is loaded from
-// memory once per step (plus two halo columns), the j +- 1 neighbours come
-// from DPP wavefront shifts, and the Dirichlet ring is evaluated in place.
-// TI: input element type, TO: output element type.
+// Preparation step of the FP32 increment form.  Each wavefront owns a strip
+// of 64 consecutive interior columns and a chunk of `rows` consecutive rows of
+// one slice.  It walks down the rows keeping rows i-1, i, i+1 of the FP64 base
+// in registers: every value is loaded once (plus two halo columns), the j +- 1
+// neighbours come from DPP wavefront shifts, and the Dirichlet ring is
+// evaluated in place at the slice's start time.  Writes dt*L b, rounded once
+// to FP32, to both outputs.
 // ---------------------------------------------------------------------------
-template <int MODE, bool CHEAP, typename TI, typename TO>
-__global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
-                                                      const float* __restrict__ lb,
-                                                      TO* __restrict__ out,
+template <bool CHEAP>
+__global__ __launch_bounds__(kBlock) void k_fine_prep(const double* __restrict__ in,
+                                                      float* __restrict__ out,
                                                       float* __restrict__ out2, StepArgs a) {
 #pragma clang fp contract(on)
     const int lane = threadIdx.x & 63;
@@ -64,33 +64,28 @@ __global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
     const int M = a.g.n;
     const int P = a.g.pitch;
     const int n = a.first + s;
-    const double Tn = n * a.dT;
-    const double tau = Tn + a.step * a.dt;
+    const double tau = n * a.dT;
     const double disc_tau = exp(-a.bc.r * tau);
-    const double disc_T = exp(-a.bc.r * Tn);
     const int j0 = 1 + strip * kWave;
     const int j = j0 + lane;
     const int ia = 1 + chunk * a.rows;
     const int ib = min(ia + a.rows, M - 1);
-    const TI* src = in + (long long)s * a.g.stride;
+    const double* src = in + (long long)s * a.g.stride;
 
-    // Ring value of the stencil input at node (i, jj).
-    auto ring = [&](int i, int jj) -> TI {
-        const double x = i * a.bc.h, y = jj * a.bc.h;
-        double v = ring_value<CHEAP>(a.bc, x, y, tau, disc_tau);
-        if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, x, y, Tn, disc_T);
-        return (TI)v;
+    // ring value of the base at node (i, jj)
+    auto ring = [&](int i, int jj) -> double {
+        return ring_value<CHEAP>(a.bc, i * a.bc.h, jj * a.bc.h, tau, disc_tau);
     };
-    // Row i of the input as (left, centre, right) for this lane's column j.
-    auto load_row = [&](int i, TI& l, TI& c, TI& r) {
+    // row i of the base as (left, centre, right) for this lane's column j
+    auto load_row = [&](int i, double& l, double& c, double& r) {
         const bool ringrow = (i == 0) || (i == M - 1);
-        const TI* row = src + (long long)(i - 1) * P;
+        const double* row = src + (long long)(i - 1) * P;
         if (ringrow) {
-            c = (j <= M - 1) ? ring(i, j) : TI(0);
+            c = (j <= M - 1) ? ring(i, j) : 0.0;
         } else {
-            c = (j <= M - 2) ? row[j - 1] : (j == M - 1 ? ring(i, j) : TI(0));
+            c = (j <= M - 2) ? row[j - 1] : (j == M - 1 ? ring(i, j) : 0.0);
         }
-        TI h = TI(0);
+        double h = 0.0;
         const int jh = (lane == 0) ? j0 - 1 : j0 + kWave;
         if (lane < 2) {
             if (!ringrow && jh >= 1 && jh <= M - 2)
@@ -98,50 +93,40 @@ __global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
             else if (jh <= M - 1)
                 h = ring(i, jh);
         }
-        const TI hl = bcast(h, 0), hr = bcast(h, 1);
+        const double hl = bcast(h, 0), hr = bcast(h, 1);
         l = shr1(c);
         r = shl1(c);
         if (lane == 0) l = hl;
         if (lane == kWave - 1) r = hr;
     };
 
-    using T = TI;
     const double fj = (double)j;
-    const T bj = (T)(a.c.a2 * fj * fj);
-    const T nj = (T)(a.c.hr * fj);
-    const T gj = (T)(a.c.g12 * fj);
-    const T rr = (T)a.c.r;
-    const T dt = (T)a.dt;
+    const double bj = a.c.a2 * fj * fj;
+    const double nj = a.c.hr * fj;
+    const double gj = a.c.g12 * fj;
+    const double rr = a.c.r;
     const bool active = (j <= M - 2);
 
-    T lm, cm, rm, l0, c0, r0, lp, cp, rp;
+    double lm, cm, rm, l0, c0, r0, lp, cp, rp;
     load_row(ia - 1, lm, cm, rm);
     load_row(ia, l0, c0, r0);
     for (int i = ia; i < ib; ++i) {
         load_row(i + 1, lp, cp, rp);
         const long long o = (long long)(i - 1) * P + (j - 1);
-        float lbv = 0.f;
-        if (MODE == MODE_INCR && active) lbv = lb[(long long)s * a.g.stride + o];
         const double fi = (double)i;
-        const T A = (T)(a.c.a1 * fi * fi);
-        const T Mu = (T)(a.c.hr * fi);
-        const T G = gj * (T)fi;
-        const T uxx = cp - T(2) * c0 + cm;
-        const T uyy = r0 - T(2) * c0 + l0;
-        const T uxy = rp + lm - lp - rm;
-        const T ux = cp - cm;
-        const T uy = r0 - l0;
-        const T L = A * uxx + bj * uyy + G * uxy + Mu * ux + nj * uy - rr * c0;
+        const double A = a.c.a1 * fi * fi;
+        const double Mu = a.c.hr * fi;
+        const double G = gj * fi;
+        const double uxx = cp - 2.0 * c0 + cm;
+        const double uyy = r0 - 2.0 * c0 + l0;
+        const double uxy = rp + lm - lp - rm;
+        const double ux = cp - cm;
+        const double uy = r0 - l0;
+        const double L = A * uxx + bj * uyy + G * uxy + Mu * ux + nj * uy - rr * c0;
         if (active) {
-            TO* dst = out + (long long)s * a.g.stride + o;
-            if (MODE == MODE_DIRECT) {
-                *dst = (TO)(c0 + dt * L);
-            } else if (MODE == MODE_INCR) {
-                *dst = (TO)(c0 + dt * ((T)lbv + L));
-            } else {  // MODE_PREP: TO = float, L evaluated in FP64
-                *dst = (TO)L;
-                out2[(long long)s * a.g.stride + o] = (float)(a.dt * (double)L);
-            }
+            const float v = (float)(a.dt * L);
+            out[(long long)s * a.g.stride + o] = v;
+            out2[(long long)s * a.g.stride + o] = v;
         }
         lm = l0; cm = c0; rm = r0;
         l0 = lp; c0 = cp; r0 = rp;
@@ -162,13 +147,23 @@ __global__ __launch_bounds__(kBlock) void k_fine_step(const TI* __restrict__ in,
 // each side for the same reason.  Each input element is read once and each
 // output element written once per S steps.  The Dirichlet ring of every level
 // is evaluated in place at that level's time.
-// MODE_INCR: FP32 increments d over an FP64 base (d+ = d + dt (Lb + L d));
-// MODE_DIRECT: FP64 state (u+ = u + dt L u).
+// MODE_INCR: FP32 increments d over an FP64 base (d+ = d + dt (Lb + L d), with
+// dt Lb stored); MODE_DIRECT: FP64 state (u+ = u + dt L u).
+//
+// The update is applied as neighbour weights with dt folded in:
+//   u+ = [dt Lb] + (cR_i - b2_j) u + wP_i u_{i+1} + wM_i u_{i-1} + wR_j u_{j+1}
+//        + wL_j u_{j-1} + gI_i j (mixed four-corner difference),
+// cR = 1 - dt (2 alpha_i + r), wP/wM = dt (alpha_i +- mu_i), gI = dt rho s1 s2 i / 4
+// per row (uniform: read from the table `wt` with scalar loads), b2 = 2 dt beta_j,
+// wR/wL = dt (beta_j +- nu_j) per column (registers).  The j +- 1 neighbours
+// enter as DPP operands of the multiply-adds, so a point-step is eleven vector
+// operations.  Every row path evaluates the same expressions in the same order.
 // ---------------------------------------------------------------------------
 template <int MODE, bool CHEAP, typename T, int S, int PF>
 __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                                                     const float* __restrict__ lb,
-                                                    T* __restrict__ out, StepArgs a) {
+                                                    T* __restrict__ out,
+                                                    const T* __restrict__ wt, StepArgs a) {
     // multiply-adds are fused only within a statement, so every instance (S,
     // row path) evaluates a point-step with the same roundings: the result does
     // not depend on the launch geometry
@@ -238,13 +233,10 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     const bool ring_lane = jl == jring;   // P_MID: this lane is the ring column
     const int rlane = rc_right ? RS : 0;    // P_MID: first ring lane of that column
 
+    // column weights (FP64, then rounded once)
     const T fj = (T)jl;
-    const T a1 = (T)a.c.a1, hr = (T)a.c.hr;
-    const T bj = (T)a.c.a2 * fj * fj;
-    const T nj = hr * fj;
-    const T gj = (T)a.c.g12 * fj;
-    const T rr = (T)a.c.r;
-    const T dt = (T)a.dt;
+    const double Bj = a.c.a2 * (double)jl * (double)jl, Nj = a.c.hr * (double)jl;
+    const T wR = (T)(a.dt * (Bj + Nj)), wL = (T)(a.dt * (Bj - Nj)), b2 = (T)(2.0 * a.dt * Bj);
 
     // Window of level q (0..S-1): three rows in slots 0..2; with the row loop
     // unrolled by 3 the newest row of iteration x sits in slot x % 3, so
@@ -341,14 +333,21 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
         for (int q = 1; q <= S; ++q) {
             const int row = x - q;
             const T um = wc[q - 1][K2], u0 = wc[q - 1][K1], up = wc[q - 1][K];
-            const T l0 = shr1(u0), r0 = shl1(u0);
+            // row weights: uniform row index, scalar loads (clamped rows feed
+            // only values that are replaced by ring values or zero)
+            const T* w = wt + 4 * min(max(row, 0), M - 1);
+            const T wP = w[0], wM = w[1], cR = w[2], gI = w[3];
             const T dd = up - um;
             const T mix = shl1(dd) - shr1(dd);   // (r+ - l+) - (r- - l-)
-            const T fi = (T)row;
-            const T A = a1 * fi * fi, Mu = hr * fi, G = gj * fi;
-            const T L = A * (up - T(2) * u0 + um) + bj * (r0 - T(2) * u0 + l0) + G * mix +
-                        Mu * dd + nj * (r0 - l0) - rr * u0;
-            T c = (MODE == MODE_INCR) ? u0 + dt * ((T)lbw[q - 1] + L) : u0 + dt * L;
+            const T G = gI * fj;
+            T acc = (MODE == MODE_INCR) ? cR * u0 + (T)lbw[q - 1] : cR * u0;
+            acc = acc - b2 * u0;
+            acc = acc + wP * up;
+            acc = acc + wM * um;
+            acc = acc + wR * shl1(u0);
+            acc = acc + wL * shr1(u0);
+            acc = acc + G * mix;
+            T c = acc;
             if (PATH == P_MID) {
                 const T rvq = mid_ring(q);
                 c = ring_lane ? rvq : c;
@@ -774,73 +773,84 @@ __global__ void k_finalize(const double* __restrict__ Uin, const float* __restri
 // ---------------------------------------------------------------------------
 static int step_waves(const StepArgs& a) { return a.count * a.nchunks * a.nstrips; }
 
-template <int MODE, typename TI, typename TO>
-static hipError_t launch_step(const TI* in, const float* lb, TO* out, float* out2,
-                              const StepArgs& a, hipStream_t st) {
-    const int blocks = (step_waves(a) + 3) / 4;
-    if (a.bc.kind == 2)
-        hipLaunchKernelGGL((k_fine_step<MODE, false, TI, TO>), dim3(blocks), dim3(kBlock), 0, st,
-                           in, lb, out, out2, a);
-    else
-        hipLaunchKernelGGL((k_fine_step<MODE, true, TI, TO>), dim3(blocks), dim3(kBlock), 0, st,
-                           in, lb, out, out2, a);
-    return hipGetLastError();
-}
+static int prep_blocks(const StepArgs& a) { return (step_waves(a) + 3) / 4; }
 
 // Rows in flight per wavefront: 3 measured faster than 6 on the 513^2 x 64
 // slice workload (deeper queues cost occupancy).
 constexpr int kTbPrefetch = 3;
 
 template <int MODE, typename T, int S>
-static void launch_tb_s(const T* in, const float* lb, T* out, const StepArgs& a, hipStream_t st) {
+static void launch_tb_s(const T* in, const float* lb, T* out, const T* wt, const StepArgs& a,
+                        hipStream_t st) {
     const int blocks = (step_waves(a) + 3) / 4;
     if (a.bc.kind == 2)
         hipLaunchKernelGGL((k_fine_tb<MODE, false, T, S, kTbPrefetch>), dim3(blocks), dim3(kBlock),
-                           0, st, in, lb, out, a);
+                           0, st, in, lb, out, wt, a);
     else
         hipLaunchKernelGGL((k_fine_tb<MODE, true, T, S, kTbPrefetch>), dim3(blocks), dim3(kBlock),
-                           0, st, in, lb, out, a);
+                           0, st, in, lb, out, wt, a);
 }
 
 template <int MODE, typename T>
-static hipError_t launch_tb(const T* in, const float* lb, T* out, const StepArgs& a, int S,
-                            hipStream_t st) {
+static hipError_t launch_tb(const T* in, const float* lb, T* out, const T* wt, const StepArgs& a,
+                            int S, hipStream_t st) {
     switch (S) {
-        case 1: launch_tb_s<MODE, T, 1>(in, lb, out, a, st); break;
-        case 2: launch_tb_s<MODE, T, 2>(in, lb, out, a, st); break;
-        case 3: launch_tb_s<MODE, T, 3>(in, lb, out, a, st); break;
-        case 4: launch_tb_s<MODE, T, 4>(in, lb, out, a, st); break;
-        case 5: launch_tb_s<MODE, T, 5>(in, lb, out, a, st); break;
-        case 6: launch_tb_s<MODE, T, 6>(in, lb, out, a, st); break;
-        case 7: launch_tb_s<MODE, T, 7>(in, lb, out, a, st); break;
-        case 8: launch_tb_s<MODE, T, 8>(in, lb, out, a, st); break;
+        case 1: launch_tb_s<MODE, T, 1>(in, lb, out, wt, a, st); break;
+        case 2: launch_tb_s<MODE, T, 2>(in, lb, out, wt, a, st); break;
+        case 3: launch_tb_s<MODE, T, 3>(in, lb, out, wt, a, st); break;
+        case 4: launch_tb_s<MODE, T, 4>(in, lb, out, wt, a, st); break;
+        case 5: launch_tb_s<MODE, T, 5>(in, lb, out, wt, a, st); break;
+        case 6: launch_tb_s<MODE, T, 6>(in, lb, out, wt, a, st); break;
+        case 7: launch_tb_s<MODE, T, 7>(in, lb, out, wt, a, st); break;
+        case 8: launch_tb_s<MODE, T, 8>(in, lb, out, wt, a, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fine_tb_f32(const float* in, const float* lb, float* out, const StepArgs& a,
+hipError_t launch_fine_tb_f32(const float* in, const float* lb, float* out, const float* wt,
+                              const StepArgs& a, int S, hipStream_t st) {
+    return launch_tb<MODE_INCR, float>(in, lb, out, wt, a, S, st);
+}
+
+hipError_t launch_fine_tb_f64(const double* in, double* out, const double* wt, const StepArgs& a,
                               int S, hipStream_t st) {
-    return launch_tb<MODE_INCR, float>(in, lb, out, a, S, st);
+    return launch_tb<MODE_DIRECT, double>(in, nullptr, out, wt, a, S, st);
 }
 
-hipError_t launch_fine_tb_f64(const double* in, double* out, const StepArgs& a, int S,
-                              hipStream_t st) {
-    return launch_tb<MODE_DIRECT, double>(in, nullptr, out, a, S, st);
+// Row weights of the temporally blocked step for rows 0..n-1 (see k_fine_tb):
+// [wP, wM, cR, gI] = [dt (alpha + mu), dt (alpha - mu), 1 - dt (2 alpha + r),
+// dt rho s1 s2 i / 4], evaluated in FP64 and rounded once to T.
+template <typename T>
+__global__ void k_row_weights(T* __restrict__ wt, int n, Coef c, double dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double A = c.a1 * (double)i * (double)i, Mu = c.hr * (double)i;
+    wt[4 * i] = (T)(dt * (A + Mu));
+    wt[4 * i + 1] = (T)(dt * (A - Mu));
+    wt[4 * i + 2] = (T)(1.0 - dt * (2.0 * A + c.r));
+    wt[4 * i + 3] = (T)(dt * c.g12 * (double)i);
 }
 
-hipError_t launch_fine_step_f64(const double* in, double* out, const StepArgs& a, hipStream_t st) {
-    return launch_step<MODE_DIRECT, double, double>(in, nullptr, out, nullptr, a, st);
-}
-
-hipError_t launch_fine_step_f32(const float* in, const float* lb, float* out, const StepArgs& a,
-                                hipStream_t st) {
-    return launch_step<MODE_INCR, float, float>(in, lb, out, nullptr, a, st);
+hipError_t launch_row_weights(void* wt, int n, const Coef& c, double dt, int fp32, hipStream_t st) {
+    if (fp32)
+        hipLaunchKernelGGL(k_row_weights<float>, dim3((n + 255) / 256), dim3(256), 0, st,
+                           (float*)wt, n, c, dt);
+    else
+        hipLaunchKernelGGL(k_row_weights<double>, dim3((n + 255) / 256), dim3(256), 0, st,
+                           (double*)wt, n, c, dt);
+    return hipGetLastError();
 }
 
 hipError_t launch_fine_prep(const double* base, float* lb, float* d1, const StepArgs& a,
                             hipStream_t st) {
-    return launch_step<MODE_PREP, double, float>(base, nullptr, lb, d1, a, st);
+    if (a.bc.kind == 2)
+        hipLaunchKernelGGL(k_fine_prep<false>, dim3(prep_blocks(a)), dim3(kBlock), 0, st, base, lb,
+                           d1, a);
+    else
+        hipLaunchKernelGGL(k_fine_prep<true>, dim3(prep_blocks(a)), dim3(kBlock), 0, st, base, lb,
+                           d1, a);
+    return hipGetLastError();
 }
 
 // the coarse side compiled into the chain kernel (the at-scale coarse grid)

@@ -24,11 +24,15 @@
 #include "internal.hpp"
 
 namespace pr {
-hipError_t launch_fine_step_f64(const double*, double*, const StepArgs&, hipStream_t);
-hipError_t launch_fine_step_f32(const float*, const float*, float*, const StepArgs&, hipStream_t);
 hipError_t launch_fine_prep(const double*, float*, float*, const StepArgs&, hipStream_t);
-hipError_t launch_fine_tb_f32(const float*, const float*, float*, const StepArgs&, int, hipStream_t);
-hipError_t launch_fine_tb_f64(const double*, double*, const StepArgs&, int, hipStream_t);
+hipError_t launch_fine_tb_f32(const float*, const float*, float*, const float*, const StepArgs&, int,
+                              hipStream_t);
+hipError_t launch_fine_tb_f64(const double*, double*, const double*, const StepArgs&, int,
+                              hipStream_t);
+hipError_t launch_row_weights(void*, int, const Coef&, double, int, hipStream_t);
+int krylov_blocks_per_slice(const Grid&, int);
+hipError_t krylov_step(double*, const KrylovBufs&, const KrylovArgs&, int, int, int*, int*,
+                       hipStream_t);
 hipError_t chain_set_lds(int);
 hipError_t launch_chain(const double*, double*, double*, double*, float*, const ChainArgs&,
                         hipStream_t);
@@ -104,9 +108,9 @@ double gershgorin_dt(int n, const pr_model& m) {
 }
 
 struct Layout {
-    uint64_t Ua, Ub, dA, dB, Lb, wA, wB, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
+    uint64_t Ua, Ub, dA, dB, Lb, wA, wB, wt, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
         lw0, lw1, lwb, Sr, Sp, fwf, fT, fwc, fwc1, fTp, fin, fmeta, fout, fvc0, fvc1, flw0, flw1,
-        flwb, fwb, gst, foldc, total;
+        flwb, fwb, gst, foldc, kR, kRH, kP0, kP1, kV0, kV1, kS, kT, kpA, kpB, kpC, ksc, kdone, total;
 };
 
 bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
@@ -134,6 +138,15 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
         return fail("cfl must be in (0, 1] when a step count is planned");
     if (o->max_iters < 0) return fail("max_iters must be >= 0");
     if (!(o->tol >= 0.0)) return fail("tol must be >= 0");
+    if (o->fine_scheme != PR_FINE_EXPLICIT && o->fine_scheme != PR_FINE_IMPLICIT)
+        return fail("unknown fine_scheme");
+    if (o->fine_scheme == PR_FINE_IMPLICIT) {
+        if (o->precision != PR_FP64) return fail("PR_FINE_IMPLICIT runs in PR_FP64");
+        if (o->fine_steps < 1) return fail("PR_FINE_IMPLICIT needs fine_steps >= 1");
+        if (o->flags & PR_FLAG_GRAPH) return fail("PR_FINE_IMPLICIT cannot be graph-captured");
+        if (!(o->krylov_tol >= 0.0 && o->krylov_tol < 1.0)) return fail("krylov_tol must be in [0, 1)");
+        if (o->krylov_max_iters < 0) return fail("krylov_max_iters must be >= 0");
+    }
     return true;
 }
 
@@ -157,6 +170,7 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.Lb = take(fp32 ? N * sf : 0);
     L.wA = take(fp32 ? 0 : N * sd);
     L.wB = take(fp32 ? 0 : N * sd);
+    L.wt = take((uint64_t)g->n * 4 * 8);   // row weights of the step kernel
     L.Gold = take(N * nc * nc * 8);
     L.dcor = take(N * nc * nc * 8);
     L.cst = take(nc * nc * 8);
@@ -192,6 +206,22 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.flw1 = take(fno ? mi * mi * 8 : 0);
     L.flwb = take(fno ? mi * mi * 8 : 0);
     L.fwb = take(fno ? mi * mi * 8 : 0);
+    // implicit F: BiCGStab vectors (N slices each), partial sums (at most one
+    // workgroup per row), per-slice scalars and the finished-slice counter
+    const bool imp = o->fine_scheme == PR_FINE_IMPLICIT;
+    L.kR = take(imp ? N * sd : 0);
+    L.kRH = take(imp ? N * sd : 0);
+    L.kP0 = take(imp ? N * sd : 0);
+    L.kP1 = take(imp ? N * sd : 0);
+    L.kV0 = take(imp ? N * sd : 0);
+    L.kV1 = take(imp ? N * sd : 0);
+    L.kS = take(imp ? N * sd : 0);
+    L.kT = take(imp ? N * sd : 0);
+    L.kpA = take(imp ? N * nf * 8 : 0);
+    L.kpB = take(imp ? N * nf * 16 : 0);
+    L.kpC = take(imp ? N * nf * 16 : 0);
+    L.ksc = take(imp ? N * sizeof(KScal) : 0);
+    L.kdone = take(imp ? 64 : 0);
     L.red = take(64);
     L.total = p;
     return L;
@@ -224,6 +254,11 @@ struct pr_solver {
     int fuse_small = 4;                // ... when a sweep has few slices (PR_STEP_FUSE_SMALL)
     int small_count = 0;               // "few": at most this many slices (PR_STEP_SMALL_COUNT;
                                        // 0: every sweep uses `fuse`)
+    bool weights_ready = false;        // row-weight table of the step kernel written
+    bool implicit = false;             // PR_FINE_IMPLICIT
+    int64_t kry_iters = 0;             // BiCGStab iterations of this call (summed over steps)
+    int kry_max = 0;                   // most iterations of one step
+    int kry_unconv = 0;                // slice-steps that stopped unconverged
     int wave_target = 6144;            // wavefronts a step launch aims for (PR_STEP_WAVES)
     int min_rows = 8;                  // shortest row chunk of a step launch (PR_STEP_MINROWS)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
@@ -292,6 +327,67 @@ StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, i
     return a;
 }
 
+// Implicit-Euler F (Eq. (fd)) over slices [first, first+count): the FP64
+// states start as copies of the bases and are stepped in place, each step a
+// BiCGStab solve of every slice at once (tmp: the single-slice temporaries).
+pr_status implicit_sweep(pr_solver* s, const double* Ubase, int first, int count, bool tmp,
+                         const double** wres, double* step_ms) {
+    const Grid& g = s->fg;
+    if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+    const long long off = tmp ? 0 : (long long)first * g.stride;
+    double* X = s->at<double>(tmp ? s->L.twA : s->L.wA) + off;
+    HIPCHK(hipMemcpyAsync(X, Ubase + (long long)first * g.stride,
+                          (size_t)count * g.stride * sizeof(double), hipMemcpyDeviceToDevice,
+                          s->stream));
+    KrylovBufs b{};
+    b.R = s->at<double>(s->L.kR);
+    b.RH = s->at<double>(s->L.kRH);
+    b.P[0] = s->at<double>(s->L.kP0);
+    b.P[1] = s->at<double>(s->L.kP1);
+    b.V[0] = s->at<double>(s->L.kV0);
+    b.V[1] = s->at<double>(s->L.kV1);
+    b.S = s->at<double>(s->L.kS);
+    b.T = s->at<double>(s->L.kT);
+    b.partA = s->at<double>(s->L.kpA);
+    b.partB = s->at<double>(s->L.kpB);
+    b.partC = s->at<double>(s->L.kpC);
+    b.sc = s->at<KScal>(s->L.ksc);
+    b.ndone = s->at<int>(s->L.kdone);
+    KrylovArgs a{};
+    a.g = g;
+    a.c = s->coef;
+    a.bc = s->bcf;
+    a.dt = s->dtF;
+    a.dT = s->dT;
+    a.first = first;
+    a.count = count;
+    a.nblk = krylov_blocks_per_slice(g, count);
+    a.rows = (g.nin + a.nblk - 1) / a.nblk;
+    a.nblk = (g.nin + a.rows - 1) / a.rows;
+    const double tol = s->opt.krylov_tol > 0.0 ? s->opt.krylov_tol : 1e-12;
+    a.tol2 = tol * tol;
+    const int maxit = s->opt.krylov_max_iters > 0 ? s->opt.krylov_max_iters : 1000;
+    for (int q = 0; q < s->mF; ++q) {
+        a.step = q;
+        int done = 0, its = 0;
+        HIPCHK(krylov_step(X, b, a, maxit, 8, &done, &its, s->stream));
+        s->kry_iters += its;
+        s->kry_max = std::max(s->kry_max, its);
+        s->kry_unconv += count - done;
+        // a slice that stopped by breakdown counts as finished in `done`; its
+        // residual is checked here so that it is reported
+        std::vector<KScal> hs((size_t)count);
+        HIPCHK(hipMemcpyAsync(hs.data(), b.sc, hs.size() * sizeof(KScal), hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        for (const KScal& k : hs)
+            if (k.breakdown && !(k.rr <= a.tol2 * k.bb)) s->kry_unconv += 1;
+    }
+    if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[5], s->stream));
+    *wres = X - off;
+    return PR_OK;
+}
+
 // F over slices [first, first+count) from base U (interior layout, slice
 // `first` at U + first*stride).  FP32: result increments land in *dres (dA or
 // dB); FP64: the state lands in *wres.  `tmp` selects the single-slice
@@ -304,6 +400,17 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
     // launches have few wavefronts; off by default, where it measured within
     // 1% of one count for every sweep)
     const int fuse = count <= s->small_count ? s->fuse_small : s->fuse;
+    if (s->implicit) return implicit_sweep(s, Ubase, first, count, tmp, wres, step_ms);
+    if (!s->weights_ready) {
+        // stream-ordered before every step launch of this solver; under graph
+        // capture the launch becomes part of the graph (which replays it before
+        // its step launches) and the flag stays clear for eager sweeps
+        HIPCHK(launch_row_weights(s->at<char>(s->L.wt), g.n, s->coef, s->dtF, s->fp32 ? 1 : 0,
+                                  s->stream));
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(hipStreamIsCapturing(s->stream, &cs));
+        if (cs == hipStreamCaptureStatusNone) s->weights_ready = true;
+    }
     if (s->fp32) {
         float* A = s->at<float>(tmp ? s->L.tA : s->L.dA) + off;
         float* B = s->at<float>(tmp ? s->L.tB : s->L.dB) + off;
@@ -317,7 +424,7 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
             const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
                             s->step_ev_used + 2 <= (int)s->step_ev.size();
             if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
-            HIPCHK(launch_fine_tb_f32(A, Lb, B, b, S, s->stream));
+            HIPCHK(launch_fine_tb_f32(A, Lb, B, s->at<float>(s->L.wt), b, S, s->stream));
             const double bytes = 12.0 * S * (double)count * g.nin * g.nin;
             if (tv) {
                 HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
@@ -345,7 +452,7 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
                             s->step_ev_used + 2 <= (int)s->step_ev.size();
             if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
             HIPCHK(launch_fine_tb_f64(q == 0 ? Ubase + (long long)first * g.stride : A,
-                                      q == 0 ? A : B, b, S, s->stream));
+                                      q == 0 ? A : B, s->at<double>(s->L.wt), b, S, s->stream));
             const double bytes = 16.0 * S * (double)count * g.nin * g.nin;
             if (tv) {
                 HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
@@ -397,7 +504,10 @@ ChainArgs chain_args(pr_solver* s, int k0, int k1, int init) {
 
 double elapsed(pr_solver* s, int a, int b) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, s->ev[a], s->ev[b]) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&ms, s->ev[a], s->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();   // an unrecorded pair is not an error of the solve
+        return 0.0;
+    }
     return ms;
 }
 
@@ -441,9 +551,22 @@ double host_ring_max(const pr_solver* s, double tau) {
     return m;
 }
 
+void reset_krylov_stats(pr_solver* s) {
+    s->kry_iters = 0;
+    s->kry_max = 0;
+    s->kry_unconv = 0;
+}
+
+void write_krylov_stats(const pr_solver* s, pr_stats* st) {
+    st->krylov_iters = s->kry_iters;
+    st->krylov_max_step = s->kry_max;
+    st->krylov_unconverged = s->kry_unconv;
+}
+
 pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
     const Grid& g = s->fg;
     double* U = s->U(0);
+    reset_krylov_stats(s);
     s->sweep_launches = 0;
     s->sweep_bytes = 0;
     HIPCHK(launch_payoff(U, g, s->bcf, s->stream));
@@ -464,6 +587,7 @@ pr_status do_serial_fine(pr_solver* s, double* v_out, pr_stats* st) {
         st->fine_point_steps = (int64_t)s->N * s->mF * g.nin * g.nin;
         st->fine_step_launches = s->sweep_launches;
         st->fine_step_bytes = s->sweep_bytes;
+        write_krylov_stats(s, st);
     }
     return PR_OK;
 }
@@ -701,6 +825,7 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
         return PR_EMODEL;
     }
     bool diverging = false;   // PR_G_FNO: non-finite, or two increments in a row growing
+    reset_krylov_stats(s);
     s->timed_launches = 0;
     s->timed_bytes = 0;
     double* Ucur = s->U(0);
@@ -798,6 +923,7 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
         st->fine_point_steps = psteps;
         st->fine_step_launches = launches;
         st->fine_step_bytes = step_bytes;
+        write_krylov_stats(s, st);
     }
     return status;
 }
@@ -848,7 +974,7 @@ pr_status parareal_plan(const pr_grid* grid, const pr_model* model, const pr_opt
     if (coarse_steps) *coarse_steps = mg;
     if (dt_stable_fine) *dt_stable_fine = dsf;
     if (dt_stable_coarse) *dt_stable_coarse = dsc;
-    if (dT / mf > dsf) return PR_EUNSTABLE;
+    if (opt->fine_scheme != PR_FINE_IMPLICIT && dT / mf > dsf) return PR_EUNSTABLE;
     if (opt->coarse_kind == PR_G_NUMERICAL && dT / mg > dsc) return PR_EUNSTABLE;
     return PR_OK;
 }
@@ -897,6 +1023,7 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     s->N = opt->n_slices;
     s->maxit = opt->max_iters > 0 ? std::min(opt->max_iters, s->N) : s->N;
     s->fp32 = opt->precision == PR_FP32;
+    s->implicit = opt->fine_scheme == PR_FINE_IMPLICIT;
     s->lod = opt->coarse_kind == PR_G_LOD;
     s->fnog = opt->coarse_kind == PR_G_FNO;
     s->fineg = opt->coarse_kind == PR_G_FINE || s->lod || s->fnog;
@@ -1454,6 +1581,7 @@ pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* m
     pr_status st = parareal_plan(grid, model, opt, &mf, &mg, nullptr, nullptr);
     if (st != PR_OK) return st;
     if (opt->coarse_kind == PR_G_FNO) return PR_EMODEL;   // requests carry no operator
+    if (opt->fine_scheme != PR_FINE_EXPLICIT) return PR_EINVAL;   // iterations are not polled
     Req r;
     r.id = sv->next_id++;
     r.g = *grid;

@@ -29,7 +29,8 @@ def _stats_dict(st: L.pr_stats) -> dict:
                 fine_step_launches=st.fine_step_launches, fine_step_bytes=st.fine_step_bytes,
                 t_step_kernels_ms=st.t_step_kernels_ms, workspace_bytes=st.workspace_bytes,
                 coarse_fallback=st.coarse_fallback, timed_step_launches=st.timed_step_launches,
-                timed_step_bytes=st.timed_step_bytes)
+                timed_step_bytes=st.timed_step_bytes, krylov_iters=st.krylov_iters,
+                krylov_max_step=st.krylov_max_step, krylov_unconverged=st.krylov_unconverged)
 
 
 def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
@@ -43,7 +44,10 @@ def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
                      precision=L.PR_FP32 if inst.fp32 else L.PR_FP64,
                      fine_steps=inst.fine_steps_per_slice, coarse_kind=coarse_kind,
                      coarse_n=inst.coarse_M, coarse_steps=inst.coarse_steps_per_slice,
-                     cfl=inst.cfl, flags=flags, pad_=0)
+                     cfl=inst.cfl, flags=flags,
+                     fine_scheme=L.PR_FINE_IMPLICIT if getattr(inst, "implicit", False)
+                     else L.PR_FINE_EXPLICIT,
+                     krylov_tol=getattr(inst, "krylov_tol", 0.0), krylov_max_iters=0, pad2_=0)
     return g, m, p, o
 
 

@@ -42,6 +42,8 @@ class Instance:
     fp32: bool = False
     tol: float = 1e-8
     tol_relative: bool = False
+    implicit: bool = False             # implicit-Euler fine propagator (fine_steps_per_slice > 0)
+    krylov_tol: float = 0.0            # 0: the library's default
 
     def replace(self, **kw) -> "Instance":
         return replace(self, **kw)

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert {n for n, _, _ in L.SIGNATURES} == set(names)
-    assert lib.parareal_abi_version() == 1
+    assert lib.parareal_abi_version() == 2
 
 
 def test_struct_layouts_match_header(tmp_path):
