@@ -19,6 +19,7 @@
 //                  between full grids and the interior layout, finalise.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <type_traits>
 
@@ -159,6 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_fine_prep(const double* __restrict__
 // enter as DPP operands of the multiply-adds, so a point-step is eleven vector
 // operations.  Every row path evaluates the same expressions in the same order.
 // ---------------------------------------------------------------------------
+// Longest row chunk of the temporally blocked kernel and the rows of its
+// per-wavefront weight table (chunk + 3 S + 1 for S <= 8).
+constexpr int kTbMaxRows = 128;
+constexpr int kTbWRows = kTbMaxRows + 3 * 8 + 1;
+
 template <int MODE, bool CHEAP, typename T, int S, int PF>
 __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
                                                     const float* __restrict__ lb,
@@ -199,6 +205,23 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
     const T* src = in + (long long)s * a.g.stride;
     const float* lbs = lb + (long long)s * a.g.stride;
     T* dst = out + (long long)s * a.g.stride;
+    const int x0 = max(0, ia - S);
+    const int x1 = ib - 1 + S;   // last iteration (level S row ib-1)
+
+    // Row weights of rows x0 - S .. x1 - 1 (every row a level evaluates; rows
+    // outside the grid take a clamped row, whose result is never used) copied
+    // once into this wavefront's slice of LDS: a level then reads its row's
+    // four weights with one LDS load at an immediate offset.
+    using W4 = typename std::conditional<std::is_same<T, float>::value, float4, double4>::type;
+    __shared__ W4 wlds[kBlock / kWave][kTbWRows];
+    W4* wrow = wlds[threadIdx.x >> 6];
+    const int nrow = x1 - x0 + S;
+    for (int e = lane; e < nrow; e += kWave) {
+        const int rr = min(max(x0 - S + e, 0), M - 1);
+        wrow[e] = *reinterpret_cast<const W4*>(wt + 4 * rr);
+    }
+    // the LDS writes of this wavefront complete before its reads below
+    __builtin_amdgcn_s_waitcnt(0xC07F);
 
     // ring value at node (i, jl), level q; only the ring rows use it, so the
     // level's time and discount are formed on the spot
@@ -252,8 +275,6 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
         for (int k = 0; k < 3; ++k) wc[q][k] = T(0);
     }
 
-    const int x0 = max(0, ia - S);
-    const int x1 = ib - 1 + S;   // last iteration (level S row ib-1)
     // Prefetch queue: raw loads of rows x..x+PF-1 and Lb rows x-1..x+PF-2 in
     // flight (PF a multiple of 3; row x in slot x % PF).
     // Loads are unconditional, with row and column clamped into the interior,
@@ -333,10 +354,9 @@ __global__ __launch_bounds__(kBlock) void k_fine_tb(const T* __restrict__ in,
         for (int q = 1; q <= S; ++q) {
             const int row = x - q;
             const T um = wc[q - 1][K2], u0 = wc[q - 1][K1], up = wc[q - 1][K];
-            // row weights: uniform row index, scalar loads (clamped rows feed
-            // only values that are replaced by ring values or zero)
-            const T* w = wt + 4 * min(max(row, 0), M - 1);
-            const T wP = w[0], wM = w[1], cR = w[2], gI = w[3];
+            // row weights from the LDS copy: entry row - (x0 - S)
+            const W4 w = wrow[x - x0 + S - q];
+            const T wP = w.x, wM = w.y, cR = w.z, gI = w.w;
             const T dd = up - um;
             const T mix = shl1(dd) - shr1(dd);   // (r+ - l+) - (r- - l-)
             const T G = gI * fj;
@@ -779,6 +799,21 @@ static int prep_blocks(const StepArgs& a) { return (step_waves(a) + 3) / 4; }
 // slice workload (deeper queues cost occupancy).
 constexpr int kTbPrefetch = 3;
 
+// Launch geometry of k_fine_tb for S fused steps over a.count slices: strips of
+// 64 - 2S output columns; row chunks sized so that a launch has about
+// wave_target wavefronts, between min_rows and kTbMaxRows rows (rows_override
+// > 0 replaces the rule; every chunk is capped at kTbMaxRows, the rows the
+// kernel's LDS weight table holds).
+void tb_geometry(StepArgs& a, int S, int wave_target, int min_rows, int rows_override) {
+    const int W = kWave - 2 * S;
+    a.nstrips = (a.g.nin + W - 1) / W;
+    long long rows = (long long)a.g.nin * a.nstrips * a.count / wave_target;
+    rows = std::max<long long>(min_rows, std::min<long long>(kTbMaxRows, rows));
+    if (rows_override > 0) rows = std::min(rows_override, kTbMaxRows);
+    a.rows = (int)std::min<long long>(rows, a.g.nin);
+    a.nchunks = (a.g.nin + a.rows - 1) / a.rows;
+}
+
 template <int MODE, typename T, int S>
 static void launch_tb_s(const T* in, const float* lb, T* out, const T* wt, const StepArgs& a,
                         hipStream_t st) {
@@ -794,6 +829,7 @@ static void launch_tb_s(const T* in, const float* lb, T* out, const T* wt, const
 template <int MODE, typename T>
 static hipError_t launch_tb(const T* in, const float* lb, T* out, const T* wt, const StepArgs& a,
                             int S, hipStream_t st) {
+    if (a.rows > kTbMaxRows) return hipErrorInvalidValue;   // beyond the LDS weight table
     switch (S) {
         case 1: launch_tb_s<MODE, T, 1>(in, lb, out, wt, a, st); break;
         case 2: launch_tb_s<MODE, T, 2>(in, lb, out, wt, a, st); break;

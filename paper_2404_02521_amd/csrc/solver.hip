@@ -30,6 +30,7 @@ hipError_t launch_fine_tb_f32(const float*, const float*, float*, const float*, 
 hipError_t launch_fine_tb_f64(const double*, double*, const double*, const StepArgs&, int,
                               hipStream_t);
 hipError_t launch_row_weights(void*, int, const Coef&, double, int, hipStream_t);
+void tb_geometry(StepArgs&, int, int, int, int);
 int krylov_blocks_per_slice(const Grid&, int);
 hipError_t krylov_step(double*, const KrylovBufs&, const KrylovArgs&, int, int, int*, int*,
                        hipStream_t);
@@ -311,19 +312,12 @@ StepArgs step_args(pr_solver* s, const Grid& g, const Bc& bc, double dt, int fir
     return a;
 }
 
-// Launch geometry of the temporally blocked step kernel for S fused steps:
-// strips of 64 - 2S output columns, row chunks sized so that a launch has
-// enough wavefronts to fill the chip.
+// Launch geometry of the temporally blocked step kernel (tb_geometry in
+// kernels.hip): strips of 64 - 2S output columns, row chunks sized so that a
+// launch has enough wavefronts to fill the chip.
 StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, int step, int S) {
     StepArgs a = step_args(s, g, s->bcf, dt, first, count, step);
-    const int W = kWave - 2 * S;
-    a.nstrips = (g.nin + W - 1) / W;
-    const long long target = s->wave_target;
-    long long rows = (long long)g.nin * a.nstrips * count / target;
-    rows = std::max<long long>(s->min_rows, std::min<long long>(128, rows));
-    if (s->rows_override > 0) rows = s->rows_override;
-    a.rows = (int)std::min<long long>(rows, g.nin);
-    a.nchunks = (g.nin + a.rows - 1) / a.rows;
+    tb_geometry(a, S, s->wave_target, s->min_rows, s->rows_override);
     return a;
 }
 
