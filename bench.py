@@ -134,6 +134,10 @@ def main():
                     help="run only the training part of the neural coarse propagator leg")
     ap.add_argument("--largest-solve", action="store_true",
                     help="run only the 2049^2, 256-slice solve (LOD G) against serial F")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="run only the paper's cash-or-nothing benchmark leg")
+    ap.add_argument("--paper-spacings", default="1,0.5",
+                    help="grid spacings of the resolution study (1, 0.5, 0.25)")
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the 2049^2, 256-slice solve leg")
     ap.add_argument("--largest-share-only", action="store_true",
@@ -174,6 +178,10 @@ def main():
         return
     if args.largest_solve:
         print(json.dumps(largest_solve(pr)), flush=True)
+        return
+    if args.paper_only:
+        sp = tuple(float(v) for v in args.paper_spacings.split(","))
+        print(json.dumps(paper_leg(pr, sp)), flush=True)
         return
     if args.fno_train_only:
         print(json.dumps(fno_leg(pr, [], [], {}, args.fno_train_s, parareal=False)), flush=True)
@@ -316,6 +324,8 @@ def main():
         progress("step-kernel probes done")
         out["graph"] = graph_leg(pr)
         progress("graph leg done")
+        out["paper_benchmark"] = paper_leg(pr)
+        progress("paper benchmark leg done")
         if not args.no_fno:
             out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
             progress("fno leg done")
@@ -416,6 +426,150 @@ def largest_solve(pr):
         "phase_ms": {"fine": round(stn["t_fine_ms"], 1), "chain": round(stn["t_chain_ms"], 1),
                      "correct": round(stn["t_correct_ms"], 1)}}
     sn.close()
+    return out
+
+
+def paper_leg(pr, fine_spacings=(1.0, 0.5)):
+    """The paper's benchmark problem and its experiments (Sec. 3.2, Sec. 4.1,
+    Sec. 4.4, Sec. 4.5): the two-asset cash-or-nothing option on [0, 300]^2 with
+    the closed form as ring, implicit-Euler F (three steps of 1/30 per slice),
+    N = 10 slices, FP64, BiCGStab to 1e-12, with two coarse propagators on the
+    same grid and one step of 0.1 per slice: the paper's implicit Euler (a
+    BiCGStab solve per step) and the direction-split implicit Euler (LOD: two
+    sweeps of tridiagonal line solves per step, no iteration).
+
+    * c_F and c_G per slice (GPU) and the bound of Eq. (speedup) they imply;
+    * relative l2 errors of serial F and serial G against the closed form (the
+      paper prints 2.2e-3 and 1.0e-2 for its runs, Sec. 4.1), and serial F
+      against the stored FP64 oracle;
+    * convergence against serial F after each Parareal iteration K (Fig. 3);
+    * resolution (Sec. 4.4, with the LOD G): spacing 1 with N = 2, 0.5 with
+      N = 4 (and 0.25 with N = 8 when asked for), the time steps halved with
+      the grid: 5 coarse and 15 fine steps per slice;
+    * parameters (Sec. 4.5, values from its range 0.1 ... 5, with the LOD G): r, sigma1 and
+      sigma2 varied one at a time, error per K and the K that reaches 1e-8.
+
+    On one GPU all N slices of a Parareal iteration run in one batched sweep, so
+    the measured speedup over serial F is the GPU's (Eq. (speedup) bounds it
+    only through the c_G / c_F ratio)."""
+    import numpy as np
+    import torch
+    from synthetic import paper_benchmark
+
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    def run(inst, kmax, kind=pr.PR_G_IMPLICIT, timed=()):
+        """Serial F (timed on its second call), then Parareal with coarse
+        propagator `kind` and max_iters = K for K = 1..kmax: error against
+        serial F and last increment per K, and the wall time of the solves whose
+        K is in `timed` (second call)."""
+        sv = pr.Solver(inst, bc_kind=pr.PR_BC_EXACT, coarse_kind=kind)
+        sv.serial_fine()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ser = sv.serial_fine()
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t
+        sref = ser.value.clone()
+        errs, incs, ms = [], [], {}
+        for k in range(1, kmax + 1):
+            s2 = pr.Solver(inst, bc_kind=pr.PR_BC_EXACT, coarse_kind=kind, max_iters=k)
+            r = s2.solve()
+            if k in timed:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = s2.solve()
+                torch.cuda.synchronize()
+                ms[k] = (time.perf_counter() - t) * 1e3
+            errs.append(float("%.3g" % rel(r.value, sref)))
+            incs.append(float("%.3g" % r.increments[-1]))
+            s2.close()
+        progress("paper leg: M=%d N=%d r=%g s1=%g s2=%g G=%d done" % (
+            inst.M, inst.n_slices, inst.r, inst.sigma1, inst.sigma2, kind))
+        return sv, sref, t_f, errs, incs, ser.stats, ms
+
+    out = {"workload": "cash-or-nothing, [0,300]^2 spacing 1 (301^2), K1=K2=100, r=1, "
+                       "sigma=0.3/0.3, rho=0.5, T=1, c=1; implicit F 3 steps/slice, implicit G "
+                       "1 step/slice, N=10, FP64, BiCGStab tol 1e-12"}
+    inst = paper_benchmark()
+    P = inst.n_slices
+    x = torch.arange(inst.M, dtype=torch.float64, device="cuda") * (inst.s_max / (inst.M - 1))
+    payoff = ((x[:, None] >= inst.strike) & (x[None, :] >= inst.strike2)).double() * inst.cash
+    meta = {}
+    mp = os.path.join(ROOT, "tests", "golden", "bench_oracle.json")
+    if os.path.exists(mp):
+        meta = json.load(open(mp))
+
+    def serial_g(kind):
+        """The coarse propagator alone, slice by slice from the payoff (second pass timed)."""
+        g = pr.Solver(inst, bc_kind=pr.PR_BC_EXACT, coarse_kind=kind, max_iters=1)
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            u = payoff
+            for n in range(P):
+                u = g.apply(pr.PR_OP_COARSE, n, u)
+            torch.cuda.synchronize()
+            t_g = time.perf_counter() - t
+        g.close()
+        return u, t_g
+
+    def bound(cg, cf, K):   # Eq. (speedup)
+        return 1.0 / ((1.0 + K / P) * cg / cf + K / P)
+
+    t_f = None
+    for name, kind in (("implicit", pr.PR_G_IMPLICIT), ("lod", pr.PR_G_LOD)):
+        sv, sref, tf, errs, incs, st, ms = run(inst, P, kind, timed=(1, 2))
+        if t_f is None:
+            t_f = tf
+            out["serial_f_ms"] = round(t_f * 1e3, 2)
+            out["c_fine_ms_per_slice"] = round(t_f * 1e3 / P, 3)
+            out["krylov_iters_per_fine_step"] = round(st["krylov_iters"] / (P * inst.fine_steps_per_slice), 1)
+            out["krylov_unconverged"] = st["krylov_unconverged"]
+            # stored FP64 oracle solution: max-norm difference, and the oracle's
+            # relative l2 error against the closed form (the quantity Sec. 4.1
+            # prints: 2.2e-3 for F and 1.0e-2 for G in the paper's runs)
+            rl2 = {"paper_printed_f": 2.2e-3, "paper_printed_g": 1.0e-2}
+            ref = golden_oracle("paper_serial_f_301.npy")
+            if ref is not None and ref.shape == tuple(sref.shape):
+                out["serial_f_err_vs_oracle"] = float(np.abs(sref.cpu().numpy() - ref).max())
+                rl2["serial_f_oracle"] = meta.get("paper_serial_f_301.npy", {}).get("rel_l2_vs_closed_form")
+            out["rel_l2_vs_closed_form"] = rl2
+        sv.close()
+        ug, t_g = serial_g(kind)
+        cf, cg = t_f / P, t_g / P
+        row = {"c_coarse_ms_per_slice": round(cg * 1e3, 3),
+               "speedup_bound_K1": round(bound(cg, cf, 1), 3),
+               "speedup_bound_K2": round(bound(cg, cf, 2), 3),
+               "parareal_ms": {str(k): round(v, 2) for k, v in ms.items()},
+               "speedup_vs_serial_f": {str(k): round(t_f * 1e3 / v, 3) for k, v in ms.items()},
+               "convergence": {"K": list(range(1, P + 1)), "err_vs_serial_f": errs,
+                               "last_increment": incs}}
+        if kind == pr.PR_G_IMPLICIT:
+            ref = golden_oracle("paper_serial_g_301.npy")
+            if ref is not None and ref.shape == tuple(ug.shape):
+                row["serial_g_err_vs_oracle"] = float(np.abs(ug.cpu().numpy() - ref).max())
+                out["rel_l2_vs_closed_form"]["serial_g_oracle"] = meta.get(
+                    "paper_serial_g_301.npy", {}).get("rel_l2_vs_closed_form")
+        out["G_" + name] = row
+    res = []
+    for spacing, N in zip(fine_spacings, (2, 4, 8)):
+        ri = paper_benchmark(spacing=spacing, n_slices=N, fine_steps_per_slice=15,
+                             coarse_steps_per_slice=5)
+        s_, _, tf, e, _, _, _ = run(ri, N, pr.PR_G_LOD)
+        s_.close()
+        res.append({"spacing": spacing, "grid": ri.M, "N": N, "err_vs_serial_f": e,
+                    "serial_f_s": round(tf, 3)})
+    out["resolution_lod_g"] = res
+    par = []
+    for kw in (dict(r=0.1), dict(r=5.0), dict(sigma1=0.1), dict(sigma1=3.0), dict(sigma2=5.0)):
+        ri = paper_benchmark(**kw)
+        s_, _, _, e, _, _, _ = run(ri, ri.n_slices, pr.PR_G_LOD)
+        s_.close()
+        k8 = next((k + 1 for k, x in enumerate(e) if x < 1e-8), None)
+        par.append(dict(kw, err_vs_serial_f=e, K_to_1e_8=k8))
+    out["parameters_lod_g"] = par
     return out
 
 

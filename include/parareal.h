@@ -58,15 +58,22 @@ typedef enum {
 } pr_status;
 
 /* Payoff at maturity (tau = 0). */
-enum { PR_PAYOFF_BASKET_CALL = 0, /* max(w1 S1 + w2 S2 - K, 0) */
-       PR_PAYOFF_EXCHANGE = 1     /* max(S1 - S2, 0) */ };
+enum { PR_PAYOFF_BASKET_CALL = 0,    /* max(w1 S1 + w2 S2 - K, 0) */
+       PR_PAYOFF_EXCHANGE = 1,       /* max(S1 - S2, 0) */
+       PR_PAYOFF_CASH_OR_NOTHING = 2 /* the paper's benchmark option (Sec. 3.2): cash if
+                                        S1 >= strike and S2 >= strike2, else 0; ring kinds
+                                        PR_BC_EXACT (Eq. (solution), |rho| <= 0.925) or
+                                        PR_BC_DISCOUNTED_PAYOFF */ };
 
 /* Dirichlet data on the boundary ring at time-to-maturity tau. */
 enum { PR_BC_FORWARD_INTRINSIC = 0, /* basket: max(w1 S1 + w2 S2 - K e^{-r tau}, 0);
                                        exchange: max(S1 - S2, 0) */
        PR_BC_DISCOUNTED_PAYOFF = 1, /* e^{-r tau} * payoff(S1, S2) */
        PR_BC_EXACT = 2              /* exchange: Margrabe's formula; basket with w2 = 0:
-                                       w1 * BlackScholesCall(S1; K/w1) */ };
+                                       w1 * BlackScholesCall(S1; K/w1); cash-or-nothing:
+                                       cash e^{-r tau} B(d1, d2; rho), Eq. (solution), with the
+                                       bivariate normal CDF B by Plackett's identity and a
+                                       20-point Gauss-Legendre rule */ };
 
 /* Coarse propagator. */
 enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilinear */
@@ -80,10 +87,14 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
                               solve restarts with PR_G_LOD (coarse_steps, default 4) and reports
                               pr_stats.coarse_fallback = 1; the solver keeps PR_G_LOD after that */
        PR_G_FINE = 2,      /* G := F (test mode: Parareal stops after one iteration) */
-       PR_G_LOD = 3        /* implicit Euler on the fine grid with coarse_steps steps per
+       PR_G_LOD = 3,       /* implicit Euler on the fine grid with coarse_steps steps per
                               slice (default 2), split by direction: the explicit mixed
                               term, then tridiagonal x lines and y lines (Sec. 3.2's
-                              coarse propagator is implicit Euler with a larger step) */ };
+                              coarse propagator is implicit Euler with a larger step) */
+       PR_G_IMPLICIT = 4   /* the paper's numerical G (Sec. 3.2): implicit Euler of
+                              Eq. (fd) on the fine grid with coarse_steps steps per slice
+                              (default 1), each solved by the BiCGStab of PR_FINE_IMPLICIT
+                              (krylov_tol, krylov_max_iters); needs PR_FP64 */ };
 
 /* Option flags.  PR_FLAG_TIME_STEPS: bracket every 8th explicit fine-step
  * launch of each sweep (the first included) with HIP events on the solver's
@@ -134,8 +145,10 @@ typedef struct {
 typedef struct {
     int32_t kind;    /* PR_PAYOFF_* */
     int32_t bc_kind; /* PR_BC_* */
-    double w1, w2;   /* basket weights (ignored by the exchange payoff) */
-    double strike;   /* K (ignored by the exchange payoff) */
+    double w1, w2;   /* basket weights (basket call only) */
+    double strike;   /* K (basket call); K1 (cash-or-nothing) */
+    double strike2;  /* K2 (cash-or-nothing only) */
+    double cash;     /* cash amount c (cash-or-nothing only) */
 } pr_payoff;
 
 typedef struct {
@@ -153,7 +166,8 @@ typedef struct {
     uint32_t flags;         /* PR_FLAG_* bits */
     int32_t fine_scheme;    /* PR_FINE_* */
     double krylov_tol;      /* PR_FINE_IMPLICIT: relative residual ||r|| / ||b||; 0 => 1e-12 */
-    int32_t krylov_max_iters; /* PR_FINE_IMPLICIT: BiCGStab iterations per step; 0 => 1000 */
+    int32_t krylov_max_iters; /* PR_FINE_IMPLICIT: BiCGStab iterations per step;
+                                 0 => max(1000, 10 (n - 2)) */
     int32_t pad2_;
 } pr_options;
 

@@ -16,9 +16,9 @@ PR_MAX_SLICES = 1024
 PR_STATIC_SCRATCH_BYTES = 64 << 20
 
 PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_ENOTCONV, PR_ENONFINITE, PR_EMODEL = range(8)
-PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE = 0, 1
+PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE, PR_PAYOFF_CASH_OR_NOTHING = 0, 1, 2
 PR_BC_FORWARD_INTRINSIC, PR_BC_DISCOUNTED_PAYOFF, PR_BC_EXACT = 0, 1, 2
-PR_G_NUMERICAL, PR_G_FNO, PR_G_FINE, PR_G_LOD = 0, 1, 2, 3
+PR_G_NUMERICAL, PR_G_FNO, PR_G_FINE, PR_G_LOD, PR_G_IMPLICIT = 0, 1, 2, 3, 4
 PR_FP64, PR_FP32 = 0, 1
 PR_FINE_EXPLICIT, PR_FINE_IMPLICIT = 0, 1
 PR_OP_FINE, PR_OP_COARSE = 0, 1
@@ -42,7 +42,8 @@ class pr_model(C.Structure):
 
 class pr_payoff(C.Structure):
     _fields_ = [("kind", C.c_int32), ("bc_kind", C.c_int32), ("w1", C.c_double),
-                ("w2", C.c_double), ("strike", C.c_double)]
+                ("w2", C.c_double), ("strike", C.c_double), ("strike2", C.c_double),
+                ("cash", C.c_double)]
 
 
 class pr_options(C.Structure):

@@ -6,13 +6,54 @@
 
 namespace pr {
 
-// Payoff at tau = 0 (Sec. 3.2 gives the cash-or-nothing payoff; this solver
-// prices the basket call max(w1 S1 + w2 S2 - K, 0) and the exchange option
-// max(S1 - S2, 0)).
+// Payoff at tau = 0: the basket call max(w1 S1 + w2 S2 - K, 0), the exchange
+// option max(S1 - S2, 0), or the paper's two-asset cash-or-nothing option
+// (Sec. 3.2): the cash amount c if S1 >= K1 and S2 >= K2, else 0.
 __device__ __host__ inline double payoff_at(const Bc& b, double x, double y) {
+    if (b.payoff == 2) return (x >= b.K && y >= b.K2) ? b.cash : 0.0;
     double v = (b.payoff == 1) ? (x - y) : (b.w1 * x + b.w2 * y - b.K);
     return v > 0.0 ? v : 0.0;
 }
+
+// 20-point Gauss-Legendre rule on [-1, 1], computed at compile time: Newton's
+// iteration on P_20 from the usual initial guesses cos(pi (i + 3/4) / 20.5),
+// weights 2 / ((1 - x^2) P_20'(x)^2).
+struct GaussLegendre20 {
+    double x[20], w[20];
+};
+constexpr double cx_cos(double t) {   // |t| <= pi: Taylor series
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 30; ++k) {
+        term *= -t * t / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+constexpr GaussLegendre20 make_gauss_legendre20() {
+    GaussLegendre20 r{};
+    const int n = 20;
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double x = cx_cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (dx < 1e-17 && dx > -1e-17) break;
+        }
+        r.x[i] = x;
+        r.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    return r;
+}
+constexpr GaussLegendre20 kGL20 = make_gauss_legendre20();
 
 __device__ inline double ncdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
 
@@ -36,9 +77,48 @@ __device__ inline double bs_call_d(double S, double K, double r, double s, doubl
     return S * ncdf(d1) - K * exp(-r * tau) * ncdf(d1 - sd);
 }
 
-// Closed-form ring values (Margrabe / one-asset call), kept out of line so the
-// stencil kernels do not carry their registers.
+// Bivariate standard normal CDF P(X <= h, Y <= k) for correlation |rho| <=
+// 0.925, from Plackett's identity d/drho B = phi_2(h, k; rho): with rho = sin t,
+//   B(h, k; rho) = Phi(h) Phi(k) + 1/(2 pi) int_0^{asin rho}
+//                  exp(-(h^2 - 2 h k sin t + k^2) / (2 cos^2 t)) dt,
+// the integral by the 20-point Gauss-Legendre rule (the integrand is smooth on
+// the whole interval for |rho| <= 0.925).
+template <int I = 0>
+__device__ inline double plackett_sum(double h, double k, double half) {
+    if constexpr (I < 20) {
+        const double t = half * (1.0 + kGL20.x[I]);
+        const double sn = sin(t), c2 = 1.0 - sn * sn;
+        return kGL20.w[I] * exp(-(h * h - 2.0 * h * k * sn + k * k) / (2.0 * c2)) +
+               plackett_sum<I + 1>(h, k, half);
+    } else {
+        return 0.0;
+    }
+}
+__device__ inline double bvn_lower(double h, double k, double rho) {
+    if (h == -INFINITY || k == -INFINITY) return 0.0;
+    if (h == INFINITY) return ncdf(k);
+    if (k == INFINITY) return ncdf(h);
+    const double base = ncdf(h) * ncdf(k);
+    if (rho == 0.0) return base;
+    const double half = 0.5 * asin(rho);
+    return base + half * plackett_sum(h, k, half) * 0.15915494309189533577;   // 1/(2 pi)
+}
+
+// The paper's closed form, Eq. (solution): c e^{-r tau} B(d1, d2; rho) with
+// d_i = (ln(S_i / K_i) + (r - sigma_i^2 / 2) tau) / (sigma_i sqrt(tau)).
+__device__ inline double cash_or_nothing_d(const Bc& b, double x, double y, double tau) {
+    if (tau <= 0.0) return payoff_at(b, x, y);
+    if (x <= 0.0 || y <= 0.0) return 0.0;
+    const double st = sqrt(tau);
+    const double d1 = (log(x / b.K) + (b.r - 0.5 * b.s1 * b.s1) * tau) / (b.s1 * st);
+    const double d2 = (log(y / b.K2) + (b.r - 0.5 * b.s2 * b.s2) * tau) / (b.s2 * st);
+    return b.cash * exp(-b.r * tau) * bvn_lower(d1, d2, b.rho);
+}
+
+// Closed-form ring values (Margrabe / one-asset call / cash-or-nothing), kept
+// out of line so the stencil kernels do not carry their registers.
 __device__ __noinline__ double ring_exact(const Bc& b, double x, double y, double tau) {
+    if (b.payoff == 2) return cash_or_nothing_d(b, x, y, tau);
     if (b.payoff == 1) return margrabe_d(x, y, tau, b.s1, b.s2, b.rho);
     return b.w1 * bs_call_d(x, b.K / b.w1, b.r, b.s1, tau);
 }

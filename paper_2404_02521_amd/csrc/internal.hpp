@@ -24,6 +24,8 @@ struct Bc {
     double w1, w2, K;
     double s1, s2, rho, r;
     double h;     // grid spacing of the grid this struct describes
+    double K2;    // cash-or-nothing: second strike (K is the first)
+    double cash;  // cash-or-nothing: cash amount
 };
 
 // Model coefficients in index form (h cancels): at node (i, j)
@@ -96,12 +98,14 @@ struct KScal {
     double rr;         // (r, r) when the slice finished (or at the iteration cap)
     int done;          // 1 once converged (or broke down)
     int iters;         // iterations performed
-    int breakdown;     // 1 if a denominator vanished before convergence
+    int breakdown;     // 1 if the slice stopped without meeting the tolerance
+    int verified;      // 1 once the true residual b - A x has been checked
+    int restarts;      // restarts from the true residual so far
     int pad_;
 };
 
 struct KrylovBufs {
-    double *R, *RH, *P[2], *V[2], *S, *T;   // count slices each (interior layout)
+    double *B, *R, *RH, *P[2], *V[2], *S, *T;   // count slices each (interior layout)
     double *partA, *partB, *partC;           // count * nblk (* 2) partial sums
     KScal* sc;                               // count scalar records
     int* ndone;                              // finished-slice counter (device)

@@ -18,8 +18,13 @@
 //   KC: omega = (t, s) / (t, t); x += M^-1 (alpha p + omega s);
 //       r = s - omega t;                                       partials (rh, r), (r, r)
 // p and v are read at the neighbours while their new values are written, so
-// each has two buffers.  A slice is done when (r, r) <= tol^2 (b, b); the host
-// polls the count of finished slices every few iterations.
+// each has two buffers.  A slice is done when the recursively updated (r, r)
+// is <= tol^2 (b, b); the host polls the count of finished slices every few
+// iterations.  The recursive residual can drift from b - A x after the large
+// intermediate residuals BiCGStab sometimes passes through, so every finished
+// slice is then checked with its true residual (KCHK, KVER): one that misses
+// the tolerance restarts from its current x with r = rh = b - A x (at most
+// kMaxRestarts times; it is then reported as not converged).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +36,7 @@
 namespace pr {
 
 constexpr int kKBlock = 256;
+constexpr int kMaxRestarts = 4;
 
 // Sum of `n` partial values (stride `st`) in a fixed order, broadcast to the
 // whole workgroup: thread t adds t, t + 256, ...; then a fixed tree.
@@ -103,7 +109,8 @@ __device__ inline long long koff(const Grid& g, int i, int j) {
 
 // Start of a step: b = u - (ring terms of g(tau+)), x0 = u, r = rh = b - A x0,
 // p = v = 0, scalar slots 1, partials (rh, r) = (r, r) and (b, b).
-__global__ __launch_bounds__(kKBlock) void k_kry_init(const double* __restrict__ X, double* __restrict__ R,
+__global__ __launch_bounds__(kKBlock) void k_kry_init(const double* __restrict__ X, double* __restrict__ Bv,
+                                                     double* __restrict__ R,
                                                      double* __restrict__ RH, double* __restrict__ P0,
                                                      double* __restrict__ V0, double* __restrict__ part,
                                                      KScal* __restrict__ sc, KrylovArgs a) {
@@ -134,6 +141,7 @@ __global__ __launch_bounds__(kKBlock) void k_kry_init(const double* __restrict__
             const double u = X[o];
             const double b = u - apply_row(w, i, j, ring_only);
             const double r = u - apply_row(w, i, j, xg);
+            Bv[o] = b;
             R[o] = r;
             RH[o] = r;
             P0[o] = 0.0;
@@ -154,6 +162,8 @@ __global__ __launch_bounds__(kKBlock) void k_kry_init(const double* __restrict__
             k.done = 0;
             k.iters = 0;
             k.breakdown = 0;
+            k.verified = 0;
+            k.restarts = 0;
             k.rr = 0.0;
             k.bb = 0.0;
         }
@@ -348,6 +358,76 @@ __global__ __launch_bounds__(kKBlock) void k_kry_c(double* __restrict__ X, doubl
     }
 }
 
+// KCHK: for every slice that finished and has not been checked, the true
+// residual r = b - A x (x zero on the ring: b already holds the ring terms)
+// into R and RH, p and v of the next iteration cleared (a restart begins with
+// p = r), partials (r, r) twice (the (rh, r) and (r, r) slots KA reads).
+__global__ __launch_bounds__(kKBlock) void k_kry_check(const double* __restrict__ X,
+                                                      const double* __restrict__ Bv,
+                                                      double* __restrict__ R, double* __restrict__ RH,
+                                                      double* __restrict__ Pz, double* __restrict__ Vz,
+                                                      double* __restrict__ partC,
+                                                      const KScal* __restrict__ sc, KrylovArgs a) {
+#pragma clang fp contract(on)
+    __shared__ double sm[kKBlock];
+    const int s = blockIdx.y;
+    const KScal& k = sc[s];
+    if (!k.done || k.verified) return;
+    const Grid& g = a.g;
+    const long long base = (long long)s * g.stride;
+    const int r0 = blockIdx.x * a.rows, r1 = min(r0 + a.rows, g.nin);
+    double rr = 0.0;
+    for (int row = r0; row < r1; ++row) {
+        const int i = row + 1;
+        for (int j = 1 + threadIdx.x; j <= g.n - 2; j += kKBlock) {
+            auto xz = [&](int ii, int jj) -> double {
+                return interior(g, ii, jj) ? X[base + koff(g, ii, jj)] : 0.0;
+            };
+            const long long o = base + koff(g, i, j);
+            const double r = Bv[o] - apply_row(krow(a, i, j), i, j, xz);
+            R[o] = r;
+            RH[o] = r;
+            Pz[o] = 0.0;
+            Vz[o] = 0.0;
+            rr += r * r;
+        }
+    }
+    const double p = block_sum_tree(rr, sm);
+    if (threadIdx.x == 0) {
+        double* pp = partC + ((long long)s * a.nblk + blockIdx.x) * 2;
+        pp[0] = p;
+        pp[1] = p;
+    }
+}
+
+// KVER: accept a checked slice whose true residual meets the tolerance, else
+// restart it (scalars reset, done cleared) or, past kMaxRestarts, keep it
+// stopped and flag it as not converged.
+__global__ void k_kry_verify(const double* __restrict__ partC, KScal* __restrict__ sc,
+                             int* __restrict__ ndone, KrylovArgs a) {
+    __shared__ double sm[kKBlock];
+    const int s = blockIdx.x;
+    KScal& k = sc[s];
+    if (!k.done || k.verified) return;
+    const double rr = block_sum_fixed(partC + (long long)s * a.nblk * 2 + 1, a.nblk, 2, sm);
+    if (threadIdx.x == 0) {
+        k.rr = rr;
+        if (!(rr > a.tol2 * k.bb)) {
+            k.verified = 1;
+            k.breakdown = 0;
+        } else if (k.restarts < kMaxRestarts) {
+            k.restarts += 1;
+            k.done = 0;
+            k.breakdown = 0;
+            for (int q = 0; q < 2; ++q) { k.rho[q] = 1.0; k.alpha[q] = 1.0; k.omega[q] = 1.0; }
+            atomicSub(ndone, 1);
+        } else {
+            k.verified = 1;
+            k.breakdown = 1;
+        }
+    }
+}
+
 __global__ void k_kry_zero(int* p) {
     if (threadIdx.x == 0) *p = 0;
 }
@@ -375,31 +455,41 @@ hipError_t krylov_step(double* X, const KrylovBufs& b, const KrylovArgs& a0, int
     KrylovArgs a = a0;
     const dim3 grid(a.nblk, a.count), blk(kKBlock);
     hipLaunchKernelGGL(k_kry_zero, dim3(1), dim3(64), 0, st, b.ndone);
-    hipLaunchKernelGGL(k_kry_init, grid, blk, 0, st, X, b.R, b.RH, b.P[0], b.V[0], b.partC, b.sc, a);
+    hipLaunchKernelGGL(k_kry_init, grid, blk, 0, st, X, b.B, b.R, b.RH, b.P[0], b.V[0], b.partC,
+                       b.sc, a);
     hipLaunchKernelGGL(k_kry_start, dim3(a.count), blk, 0, st, b.partC, b.sc, b.ndone, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int it = 0;
-    for (; it < max_iters; ++it) {
-        a.it = it;
-        const int cur = it & 1, nxt = cur ^ 1;
-        hipLaunchKernelGGL(k_kry_a, grid, blk, 0, st, b.R, b.RH, b.P[cur], b.P[nxt], b.V[cur],
-                           b.V[nxt], b.partC, b.partA, b.sc, b.ndone, a);
-        hipLaunchKernelGGL(k_kry_b, grid, blk, 0, st, b.R, b.V[nxt], b.S, b.T, b.partA, b.partB,
-                           b.sc, b.ndone, a);
-        hipLaunchKernelGGL(k_kry_c, grid, blk, 0, st, X, b.R, b.RH, b.P[nxt], b.S, b.T, b.partB,
-                           b.partC, b.sc, b.ndone, a);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((it + 1) % poll_every == 0) {
-            int nd = 0;
-            if ((e = hipMemcpyAsync(&nd, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
-                return e;
-            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-            if (nd >= a.count) { ++it; break; }
+    int it = 0, nd = 0;
+    for (;;) {
+        for (; it < max_iters; ++it) {
+            a.it = it;
+            const int cur = it & 1, nxt = cur ^ 1;
+            hipLaunchKernelGGL(k_kry_a, grid, blk, 0, st, b.R, b.RH, b.P[cur], b.P[nxt], b.V[cur],
+                               b.V[nxt], b.partC, b.partA, b.sc, b.ndone, a);
+            hipLaunchKernelGGL(k_kry_b, grid, blk, 0, st, b.R, b.V[nxt], b.S, b.T, b.partA,
+                               b.partB, b.sc, b.ndone, a);
+            hipLaunchKernelGGL(k_kry_c, grid, blk, 0, st, X, b.R, b.RH, b.P[nxt], b.S, b.T,
+                               b.partB, b.partC, b.sc, b.ndone, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((it + 1) % poll_every == 0) {
+                if ((e = hipMemcpyAsync(&nd, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st)) !=
+                    hipSuccess)
+                    return e;
+                if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+                if (nd >= a.count) { ++it; break; }
+            }
         }
+        // true residuals of the finished slices; restarted ones continue
+        hipLaunchKernelGGL(k_kry_check, grid, blk, 0, st, X, b.B, b.R, b.RH, b.P[it & 1],
+                           b.V[it & 1], b.partC, b.sc, a);
+        hipLaunchKernelGGL(k_kry_verify, dim3(a.count), blk, 0, st, b.partC, b.sc, b.ndone, a);
+        if ((e = hipMemcpyAsync(&nd, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        if (nd >= a.count || it >= max_iters) break;
     }
     hipLaunchKernelGGL(k_kry_final, dim3(a.count), blk, 0, st, b.partC, b.sc, a);
-    int nd = 0;
     if ((e = hipMemcpyAsync(&nd, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     *host_done = nd;

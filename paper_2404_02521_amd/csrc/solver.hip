@@ -111,7 +111,7 @@ double gershgorin_dt(int n, const pr_model& m) {
 struct Layout {
     uint64_t Ua, Ub, dA, dB, Lb, wA, wB, wt, Gold, dcor, cst, lbc, Gf, tA, tB, tLb, twA, twB, tg, red,
         lw0, lw1, lwb, Sr, Sp, fwf, fT, fwc, fwc1, fTp, fin, fmeta, fout, fvc0, fvc1, flw0, flw1,
-        flwb, fwb, gst, foldc, kR, kRH, kP0, kP1, kV0, kV1, kS, kT, kpA, kpB, kpC, ksc, kdone, total;
+        flwb, fwb, gst, foldc, kB, kR, kRH, kP0, kP1, kV0, kV1, kS, kT, kpA, kpB, kpC, ksc, kdone, total;
 };
 
 bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
@@ -122,8 +122,13 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
     if (o->n_slices < 1 || o->n_slices > PR_MAX_SLICES) return fail("n_slices out of range");
     if (o->precision != PR_FP64 && o->precision != PR_FP32) return fail("unknown precision");
     if (o->coarse_kind != PR_G_NUMERICAL && o->coarse_kind != PR_G_FINE &&
-        o->coarse_kind != PR_G_LOD && o->coarse_kind != PR_G_FNO)
+        o->coarse_kind != PR_G_LOD && o->coarse_kind != PR_G_FNO &&
+        o->coarse_kind != PR_G_IMPLICIT)
         return fail("unknown coarse_kind");
+    if (o->coarse_kind == PR_G_IMPLICIT && o->precision != PR_FP64)
+        return fail("PR_G_IMPLICIT runs in PR_FP64");
+    if (o->coarse_kind == PR_G_IMPLICIT && (o->flags & PR_FLAG_GRAPH))
+        return fail("PR_G_IMPLICIT cannot be graph-captured");
     if (o->coarse_kind == PR_G_FNO && g->n < 64)
         return fail("PR_G_FNO needs at least 64 nodes per side");
     if (o->coarse_kind == PR_G_NUMERICAL) {
@@ -145,6 +150,8 @@ bool valid_basic(const pr_grid* g, const pr_options* o, std::string* why) {
         if (o->precision != PR_FP64) return fail("PR_FINE_IMPLICIT runs in PR_FP64");
         if (o->fine_steps < 1) return fail("PR_FINE_IMPLICIT needs fine_steps >= 1");
         if (o->flags & PR_FLAG_GRAPH) return fail("PR_FINE_IMPLICIT cannot be graph-captured");
+    }
+    if (o->fine_scheme == PR_FINE_IMPLICIT || o->coarse_kind == PR_G_IMPLICIT) {
         if (!(o->krylov_tol >= 0.0 && o->krylov_tol < 1.0)) return fail("krylov_tol must be in [0, 1)");
         if (o->krylov_max_iters < 0) return fail("krylov_max_iters must be >= 0");
     }
@@ -159,7 +166,8 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     const bool gfine = o->coarse_kind == PR_G_FINE;
     const bool lod = o->coarse_kind == PR_G_LOD;
     const bool fno = o->coarse_kind == PR_G_FNO;
-    const bool fineg = gfine || lod || fno;   // G returns fine-grid states (chain over fine slices)
+    const bool gimp = o->coarse_kind == PR_G_IMPLICIT;
+    const bool fineg = gfine || lod || fno || gimp;   // G returns fine-grid states (chain over fine slices)
     const uint64_t nc = fineg ? 0 : (uint64_t)o->coarse_n;
     Layout L{};
     uint64_t p = 0;
@@ -184,7 +192,7 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.tA = take(gfine && fp32 ? sf : 0);
     L.tB = take(gfine && fp32 ? sf : 0);
     L.tLb = take(gfine && fp32 ? sf : 0);
-    L.twA = take(gfine && !fp32 ? sd : 0);
+    L.twA = take((gfine || gimp) && !fp32 ? sd : 0);
     L.twB = take(gfine && !fp32 ? sd : 0);
     L.tg = take(fineg ? sd : 0);
     L.lw0 = take(lod || fno ? sd : 0);   // PR_G_FNO falls back to LOD
@@ -209,8 +217,9 @@ Layout layout(const pr_grid* g, const pr_options* o) {
     L.fwb = take(fno ? mi * mi * 8 : 0);
     // implicit F: BiCGStab vectors (N slices each), partial sums (at most one
     // workgroup per row), per-slice scalars and the finished-slice counter
-    const bool imp = o->fine_scheme == PR_FINE_IMPLICIT;
+    const bool imp = o->fine_scheme == PR_FINE_IMPLICIT || gimp;
     L.kR = take(imp ? N * sd : 0);
+    L.kB = take(imp ? N * sd : 0);
     L.kRH = take(imp ? N * sd : 0);
     L.kP0 = take(imp ? N * sd : 0);
     L.kP1 = take(imp ? N * sd : 0);
@@ -257,6 +266,7 @@ struct pr_solver {
                                        // 0: every sweep uses `fuse`)
     bool weights_ready = false;        // row-weight table of the step kernel written
     bool implicit = false;             // PR_FINE_IMPLICIT
+    bool implicit_g = false;           // PR_G_IMPLICIT
     int64_t kry_iters = 0;             // BiCGStab iterations of this call (summed over steps)
     int kry_max = 0;                   // most iterations of one step
     int kry_unconv = 0;                // slice-steps that stopped unconverged
@@ -325,7 +335,7 @@ StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, i
 // states start as copies of the bases and are stepped in place, each step a
 // BiCGStab solve of every slice at once (tmp: the single-slice temporaries).
 pr_status implicit_sweep(pr_solver* s, const double* Ubase, int first, int count, bool tmp,
-                         const double** wres, double* step_ms) {
+                         const double** wres, double* step_ms, double dt, int steps) {
     const Grid& g = s->fg;
     if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
     const long long off = tmp ? 0 : (long long)first * g.stride;
@@ -334,6 +344,7 @@ pr_status implicit_sweep(pr_solver* s, const double* Ubase, int first, int count
                           (size_t)count * g.stride * sizeof(double), hipMemcpyDeviceToDevice,
                           s->stream));
     KrylovBufs b{};
+    b.B = s->at<double>(s->L.kB);
     b.R = s->at<double>(s->L.kR);
     b.RH = s->at<double>(s->L.kRH);
     b.P[0] = s->at<double>(s->L.kP0);
@@ -351,7 +362,7 @@ pr_status implicit_sweep(pr_solver* s, const double* Ubase, int first, int count
     a.g = g;
     a.c = s->coef;
     a.bc = s->bcf;
-    a.dt = s->dtF;
+    a.dt = dt;
     a.dT = s->dT;
     a.first = first;
     a.count = count;
@@ -360,8 +371,11 @@ pr_status implicit_sweep(pr_solver* s, const double* Ubase, int first, int count
     a.nblk = (g.nin + a.rows - 1) / a.rows;
     const double tol = s->opt.krylov_tol > 0.0 ? s->opt.krylov_tol : 1e-12;
     a.tol2 = tol * tol;
-    const int maxit = s->opt.krylov_max_iters > 0 ? s->opt.krylov_max_iters : 1000;
-    for (int q = 0; q < s->mF; ++q) {
+    // default cap: Jacobi-preconditioned BiCGStab on the stiffest steps seen
+    // (dt |L_h| ~ 1e3 at 301^2) takes up to ~3 n iterations, erratically
+    const int maxit = s->opt.krylov_max_iters > 0 ? s->opt.krylov_max_iters
+                                                   : std::max(1000, 10 * g.nin);
+    for (int q = 0; q < steps; ++q) {
         a.step = q;
         int done = 0, its = 0;
         HIPCHK(krylov_step(X, b, a, maxit, 8, &done, &its, s->stream));
@@ -394,7 +408,8 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
     // launches have few wavefronts; off by default, where it measured within
     // 1% of one count for every sweep)
     const int fuse = count <= s->small_count ? s->fuse_small : s->fuse;
-    if (s->implicit) return implicit_sweep(s, Ubase, first, count, tmp, wres, step_ms);
+    if (s->implicit)
+        return implicit_sweep(s, Ubase, first, count, tmp, wres, step_ms, s->dtF, s->mF);
     if (!s->weights_ready) {
         // stream-ordered before every step launch of this solver; under graph
         // capture the launch becomes part of the graph (which replays it before
@@ -508,6 +523,7 @@ double elapsed(pr_solver* s, int a, int b) {
 double host_ring_max(const pr_solver* s, double tau) {
     // max |g| over the fine ring at tau (host evaluation of the same closed forms)
     const Bc& b = s->bcf;
+    if (b.payoff == 2) return std::fabs(b.cash);   // the option never pays more than c
     auto payoff = [&](double x, double y) {
         double v = (b.payoff == 1) ? (x - y) : (b.w1 * x + b.w2 * y - b.K);
         return v > 0 ? v : 0.0;
@@ -672,6 +688,13 @@ pr_status fno_g(pr_solver* s, const double* Uall, int n, double* gout) {
 // The fine-grid G over slice n: g = G(U^{k+1}_n) into gout (one slice).
 pr_status fine_g(pr_solver* s, const double* Uslice_base_all, int n, double* gout) {
     if (s->fnog) return fno_g(s, Uslice_base_all, n, gout);
+    if (s->implicit_g) {
+        const double* w = nullptr;
+        pr_status r = implicit_sweep(s, Uslice_base_all, n, 1, true, &w, nullptr, s->dtG, s->mG);
+        if (r != PR_OK) return r;
+        HIPCHK(hipMemcpyAsync(gout, w, (size_t)s->fg.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+        return PR_OK;
+    }
     if (s->lod) {
         HIPCHK(launch_lod_slice(Uslice_base_all + (long long)n * s->fg.stride, gout,
                                 s->at<double>(s->L.lw0), s->at<double>(s->L.lw1),
@@ -959,6 +982,7 @@ pr_status parareal_plan(const pr_grid* grid, const pr_model* model, const pr_opt
     int mg = 0;
     double dsc = 0;
     if (opt->coarse_kind == PR_G_LOD) mg = opt->coarse_steps > 0 ? opt->coarse_steps : 2;
+    if (opt->coarse_kind == PR_G_IMPLICIT) mg = opt->coarse_steps > 0 ? opt->coarse_steps : 1;
     if (opt->coarse_kind == PR_G_NUMERICAL) {
         dsc = gershgorin_dt(opt->coarse_n, *model);
         mg = opt->coarse_steps;
@@ -993,8 +1017,16 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     if (!grid || !model || !payoff || !opt) return PR_EINVAL;
     std::string why;
     if (!valid_basic(grid, opt, &why)) return PR_EINVAL;
-    if (payoff->kind != PR_PAYOFF_BASKET_CALL && payoff->kind != PR_PAYOFF_EXCHANGE) return PR_EINVAL;
+    if (payoff->kind != PR_PAYOFF_BASKET_CALL && payoff->kind != PR_PAYOFF_EXCHANGE &&
+        payoff->kind != PR_PAYOFF_CASH_OR_NOTHING)
+        return PR_EINVAL;
     if (payoff->bc_kind < 0 || payoff->bc_kind > 2) return PR_EINVAL;
+    if (payoff->kind == PR_PAYOFF_CASH_OR_NOTHING) {
+        if (payoff->bc_kind == PR_BC_FORWARD_INTRINSIC) return PR_EINVAL;
+        if (!(payoff->strike > 0.0) || !(payoff->strike2 > 0.0) || !std::isfinite(payoff->cash))
+            return PR_EINVAL;
+        if (payoff->bc_kind == PR_BC_EXACT && !(std::fabs(model->rho) <= 0.925)) return PR_EINVAL;
+    }
     if (payoff->bc_kind == PR_BC_EXACT && payoff->kind == PR_PAYOFF_BASKET_CALL &&
         !(payoff->w2 == 0.0 && payoff->w1 > 0.0 && payoff->strike > 0.0))
         return PR_EINVAL;
@@ -1020,7 +1052,8 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     s->implicit = opt->fine_scheme == PR_FINE_IMPLICIT;
     s->lod = opt->coarse_kind == PR_G_LOD;
     s->fnog = opt->coarse_kind == PR_G_FNO;
-    s->fineg = opt->coarse_kind == PR_G_FINE || s->lod || s->fnog;
+    s->implicit_g = opt->coarse_kind == PR_G_IMPLICIT;
+    s->fineg = opt->coarse_kind == PR_G_FINE || s->lod || s->fnog || s->implicit_g;
     s->nc = s->fineg ? 0 : opt->coarse_n;
     s->q = s->fineg ? 1 : (grid->n - 1) / (opt->coarse_n - 1);
     s->mF = mf;
@@ -1036,6 +1069,8 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     b.w1 = payoff->w1;
     b.w2 = payoff->w2;
     b.K = payoff->strike;
+    b.K2 = payoff->strike2;
+    b.cash = payoff->cash;
     b.s1 = model->sigma1;
     b.s2 = model->sigma2;
     b.rho = model->rho;
@@ -1575,7 +1610,8 @@ pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* m
     pr_status st = parareal_plan(grid, model, opt, &mf, &mg, nullptr, nullptr);
     if (st != PR_OK) return st;
     if (opt->coarse_kind == PR_G_FNO) return PR_EMODEL;   // requests carry no operator
-    if (opt->fine_scheme != PR_FINE_EXPLICIT) return PR_EINVAL;   // iterations are not polled
+    // the BiCGStab steps poll their convergence on the host; the server never blocks
+    if (opt->fine_scheme != PR_FINE_EXPLICIT || opt->coarse_kind == PR_G_IMPLICIT) return PR_EINVAL;
     Req r;
     r.id = sv->next_id++;
     r.g = *grid;

@@ -38,7 +38,8 @@ def make_structs(inst, coarse_kind: int = L.PR_G_NUMERICAL, max_iters: int = 0,
     """pr_grid / pr_model / pr_payoff / pr_options from a synthetic.Instance."""
     g = L.pr_grid(inst.M, 0, inst.s_max)
     m = L.pr_model(inst.sigma1, inst.sigma2, inst.rho, inst.r, inst.T)
-    p = L.pr_payoff(inst.payoff, bc_kind, inst.w1, inst.w2, inst.strike)
+    p = L.pr_payoff(inst.payoff, bc_kind, inst.w1, inst.w2, inst.strike,
+                    getattr(inst, "strike2", 0.0), getattr(inst, "cash", 0.0))
     o = L.pr_options(n_slices=inst.n_slices, max_iters=max_iters, tol=inst.tol,
                      tol_relative=int(inst.tol_relative),
                      precision=L.PR_FP32 if inst.fp32 else L.PR_FP64,

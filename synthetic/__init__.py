@@ -18,6 +18,7 @@ import numpy as np
 
 BASKET = 0
 EXCHANGE = 1
+CASH_OR_NOTHING = 2
 
 
 @dataclass(frozen=True)
@@ -44,6 +45,8 @@ class Instance:
     tol_relative: bool = False
     implicit: bool = False             # implicit-Euler fine propagator (fine_steps_per_slice > 0)
     krylov_tol: float = 0.0            # 0: the library's default
+    strike2: float = 0.0               # cash-or-nothing: second strike (strike is the first)
+    cash: float = 0.0                  # cash-or-nothing: cash amount
 
     def replace(self, **kw) -> "Instance":
         return replace(self, **kw)
@@ -91,6 +94,23 @@ def largest_single() -> Instance:
     return Instance(M=2049, sigma1=0.35, sigma2=0.25, rho=0.3, r=0.03, T=2.0, payoff=BASKET,
                     w1=0.6, w2=0.4, strike=1.0, n_slices=256, coarse_M=257, cfl=0.9, fp32=True,
                     tol=1e-7, tol_relative=True)
+
+
+def paper_benchmark(n_slices: int = 10, fine_steps_per_slice: int = 3, spacing: float = 1.0,
+                    **kw) -> Instance:
+    """The paper's test problem (Sec. 3.2): two-asset cash-or-nothing option on
+    [0, 300]^2 with node spacing 1 (301 x 301), strikes 100 and 100, r = 1,
+    sigma1 = sigma2 = 0.3, rho = 0.5, T = 1, closed-form ring; implicit Euler
+    with coarse step 0.1 (one step per slice over 10 slices) and the fine step a
+    third of it.  The cash amount is not printed; c = 1.  `spacing` 0.5 or 0.25
+    gives the refined grids of Sec. 4.4 (601^2, 1201^2)."""
+    M = int(round(300.0 / spacing)) + 1
+    d = dict(M=M, sigma1=0.3, sigma2=0.3, rho=0.5, r=1.0, T=1.0, payoff=CASH_OR_NOTHING, w1=0.0,
+             w2=0.0, strike=100.0, strike2=100.0, cash=1.0, s_max=300.0, n_slices=n_slices,
+             coarse_M=M, fine_steps_per_slice=fine_steps_per_slice, coarse_steps_per_slice=1,
+             fp32=False, tol=0.0, tol_relative=False, implicit=True, krylov_tol=1e-12)
+    d.update(kw)
+    return Instance(**d)
 
 
 SERVE_SIDES = (129, 257, 513, 1025)

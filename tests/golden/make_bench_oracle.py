@@ -8,6 +8,11 @@ tests/golden/ (calls only oracle/; the inputs come from synthetic/).
   F on every 8th node (257 x 257).  About 7.7e12 point-steps, hours on a few
   cores; the run checkpoints the state after every slice in --ckpt and resumes
   from the last one.
+* ``paper_serial_f_301.npy`` and ``paper_serial_g_301.npy``: the paper's
+  cash-or-nothing problem (Sec. 3.2) on its 301 x 301 grid, closed-form ring,
+  implicit Euler over N = 10 slices of 0.1: serial F (three steps of 1/30 per
+  slice) and the coarse propagator alone (one step of 0.1 per slice), every node;
+  their relative l2 errors against the closed form go into the JSON.
 * ``bench_oracle.json``: the parameters, step counts and subsample of every file.
 
 Serial F is Eq. (fd)'s spatial operator with explicit Euler (Sec. 3.2) over
@@ -17,6 +22,7 @@ Run from the repository root:
 
     python tests/golden/make_bench_oracle.py --c2
     python tests/golden/make_bench_oracle.py --c5 --ckpt /tmp/c5_ckpt
+    python tests/golden/make_bench_oracle.py --paper
 """
 import argparse
 import hashlib
@@ -31,7 +37,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from synthetic import largest_single, plain_at_scale  # noqa: E402
+from oracle import cash  # noqa: E402
+from oracle import implicit  # noqa: E402
+from synthetic import largest_single, paper_benchmark, plain_at_scale  # noqa: E402
 
 
 def problem(inst):
@@ -79,6 +87,7 @@ def main():
     ap.add_argument("--c2", action="store_true")
     ap.add_argument("--c5", action="store_true")
     ap.add_argument("--seeds", type=int, nargs="*", default=list(range(8)))
+    ap.add_argument("--paper", action="store_true")
     ap.add_argument("--ckpt", default=None, help="checkpoint directory of the 2049^2 run")
     args = ap.parse_args()
     mpath = os.path.join(HERE, "bench_oracle.json")
@@ -104,6 +113,26 @@ def main():
         record(meta, name, inst, mF, 8, sub)
         json.dump(meta, open(mpath, "w"), indent=1, sort_keys=True)
         log("%s written" % name)
+    if args.paper:
+        inst = paper_benchmark()
+        p = cash.CashProblem(M=inst.M, s_max=inst.s_max, sigma1=inst.sigma1,
+                             sigma2=inst.sigma2, rho=inst.rho, r=inst.r, K1=inst.strike,
+                             K2=inst.strike2, cash=inst.cash)
+        ex = cash.exact_grid(p, inst.T)
+        for tag, m in (("f", inst.fine_steps_per_slice), ("g", inst.coarse_steps_per_slice)):
+            t = time.time()
+            u = implicit.serial_fine(p, inst.n_slices, inst.T, m, ring=cash.ring_grid,
+                                     init=cash.payoff_grid)
+            name = "paper_serial_%s_301.npy" % tag
+            np.save(os.path.join(HERE, name), u)
+            meta[name] = dict(M=inst.M, n_slices=inst.n_slices, T=inst.T, steps_per_slice=m,
+                              sigma1=inst.sigma1, sigma2=inst.sigma2, rho=inst.rho, r=inst.r,
+                              K1=inst.strike, K2=inst.strike2, cash=inst.cash, every=1,
+                              shape=list(u.shape), rel_l2_vs_closed_form=cash.rel_l2(u, ex),
+                              sha256=hashlib.sha256(u.tobytes()).hexdigest())
+            log("%s: rel l2 vs closed form %.4e, %.1f s" % (name, cash.rel_l2(u, ex),
+                                                            time.time() - t))
+        json.dump(meta, open(mpath, "w"), indent=1, sort_keys=True)
 
 
 if __name__ == "__main__":

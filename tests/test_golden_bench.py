@@ -1,11 +1,12 @@
 """Bench-size results against the FP64 oracle's stored serial fine solutions.
 
 tests/golden/make_bench_oracle.py wrote them from oracle/ alone: serial F of
-the 513^2 x 64-slice at-scale problems (seeds 0-7, every 4th node) and of the
-2049^2 x 256-slice single solve (every 8th node).  The CPU tests re-run the
-cheapest seed through the oracle and check the record; the GPU tests hold the
-GPU's serial F and Parareal results at these sizes to 1e-5 relative max-norm
-of the oracle (FP32 increments over 18k-110k explicit steps).
+the 513^2 x 64-slice at-scale problems (seeds 0-7, every 4th node), of the
+2049^2 x 256-slice single solve (every 8th node), and serial F and serial G of
+the paper's cash-or-nothing problem on 301^2 (every node).  The CPU tests
+re-run the cheapest records through the oracle and check them; the GPU tests
+hold the GPU's serial F and Parareal results at these sizes to 1e-5 relative
+max-norm of the oracle (FP32 increments over 18k-1.8M explicit steps).
 """
 import hashlib
 import json
@@ -16,7 +17,9 @@ import pytest
 
 import oracle
 from helpers import oproblem, rel_max, say
-from synthetic import largest_single, plain_at_scale
+from oracle import cash
+from oracle import implicit as im
+from synthetic import largest_single, paper_benchmark, plain_at_scale
 
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 META = json.load(open(os.path.join(HERE, "bench_oracle.json")))
@@ -28,13 +31,40 @@ def golden(name):
 
 
 def test_records_match_their_metadata():
+    assert {"c5_serial_f_257.npy", "paper_serial_f_301.npy", "paper_serial_g_301.npy"} <= set(META)
     for name, m in META.items():
         a = golden(name)
         assert list(a.shape) == m["shape"], name
         assert hashlib.sha256(a.tobytes()).hexdigest() == m["sha256"], name
-        inst = largest_single() if name.startswith("c5") else plain_at_scale(int(name[-5]))
-        for k in ("M", "n_slices", "T", "sigma1", "sigma2", "rho", "r", "w1", "w2", "strike"):
-            assert m[k] == getattr(inst, k), (name, k)
+        if name.startswith("paper"):
+            inst = paper_benchmark()
+            keys = dict(K1="strike", K2="strike2", cash="cash")
+            for k in ("M", "n_slices", "T", "sigma1", "sigma2", "rho", "r"):
+                keys[k] = k
+        else:
+            inst = largest_single() if name.startswith("c5") else plain_at_scale(int(name[-5]))
+            keys = {k: k for k in ("M", "n_slices", "T", "sigma1", "sigma2", "rho", "r", "w1",
+                                   "w2", "strike")}
+        for k, attr in keys.items():
+            assert m[k] == getattr(inst, attr), (name, k)
+
+
+def cash_problem(inst):
+    return cash.CashProblem(M=inst.M, s_max=inst.s_max, sigma1=inst.sigma1, sigma2=inst.sigma2,
+                            rho=inst.rho, r=inst.r, K1=inst.strike, K2=inst.strike2,
+                            cash=inst.cash)
+
+
+def test_paper_serial_g_reproduced_by_the_oracle():
+    """Serial G of the paper's problem (10 implicit steps of 0.1 on 301^2)
+    recomputed: bitwise the stored record; its relative l2 error against the
+    closed form is the one recorded."""
+    inst = paper_benchmark()
+    p = cash_problem(inst)
+    u = im.serial_fine(p, inst.n_slices, inst.T, 1, ring=cash.ring_grid, init=cash.payoff_grid)
+    assert np.array_equal(u, golden("paper_serial_g_301.npy"))
+    m = META["paper_serial_g_301.npy"]
+    assert m["rel_l2_vs_closed_form"] == cash.rel_l2(u, cash.exact_grid(p, inst.T))
 
 
 def test_c2_seed3_reproduced_by_the_oracle():
@@ -60,3 +90,19 @@ def test_bench_size_against_oracle(seed):
     assert rel_max(ser, ref) <= FP32_TOL
     assert rel_max(par, ref) <= FP32_TOL
     s.close()
+
+
+@pytest.mark.gpu
+def test_largest_serial_f_against_oracle():
+    """2049^2 x 256 slices (7207 explicit steps per slice, 1.8M steps): the GPU's
+    FP32-increment serial F within 1e-5 relative of the FP64 oracle on every
+    8th node."""
+    import paper_2404_02521_amd as pr
+    inst = largest_single()
+    say("largest serial F vs oracle")
+    s = pr.Solver(inst)
+    ser = s.serial_fine().value.cpu().numpy()[::8, ::8]
+    s.close()
+    err = rel_max(ser, golden("c5_serial_f_257.npy"))
+    print("2049^2 serial F vs oracle: %.3e" % err)
+    assert err <= FP32_TOL
