@@ -136,6 +136,10 @@ def main():
                     help="run only the 2049^2, 256-slice solve (LOD G) against serial F")
     ap.add_argument("--paper-only", action="store_true",
                     help="run only the paper's cash-or-nothing benchmark leg")
+    ap.add_argument("--three-asset-only", action="store_true",
+                    help="run only the three-asset leg")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg")
     ap.add_argument("--paper-spacings", default="1,0.5",
                     help="grid spacings of the resolution study (1, 0.5, 0.25)")
     ap.add_argument("--no-largest", action="store_true",
@@ -178,6 +182,12 @@ def main():
         return
     if args.largest_solve:
         print(json.dumps(largest_solve(pr)), flush=True)
+        return
+    if args.three_asset_only:
+        print(json.dumps(three_asset_leg(pr)), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps(serving_leg(pr)), flush=True)
         return
     if args.paper_only:
         sp = tuple(float(v) for v in args.paper_spacings.split(","))
@@ -315,6 +325,27 @@ def main():
             "timed_launches": steps_launch, "all_launches": all_launch},
     }
     if not args.no_check:
+        # the same timed solves with the coarse chain after each whole fine sweep
+        # (no overlap of chain and sweep): what the overlapped schedule gains
+        ser_solvers = {s: pr.Solver(inst, device=dev, max_iters=args.max_iters,
+                                    flags=pr.PR_FLAG_SERIAL_CHAIN)
+                       for s, inst in zip(seeds, insts)}
+        ser_solvers[seeds[0]].solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ch = 0.0
+        for k in range(args.steps):
+            ch += ser_solvers[seeds[k % len(seeds)]].solve().stats["t_chain_ms"]
+        torch.cuda.synchronize()
+        t_ser = time.perf_counter() - t1
+        for sv in ser_solvers.values():
+            sv.close()
+        out["chain_overlap"] = {
+            "overlapped_solves_per_s": round(value, 4),
+            "serial_chain_solves_per_s": round(args.steps / t_ser, 4),
+            "exposed_chain_ms_per_solve": round(chain_ms / args.steps, 2),
+            "serial_chain_ms_per_solve": round(ch / args.steps, 2)}
+        progress("serial-chain comparison done")
         out["lod_coarse"] = lod_leg(pr, insts, seeds, serial_ref)
         progress("lod leg done")
         out["serving"] = serving_leg(pr)
@@ -326,6 +357,8 @@ def main():
         progress("graph leg done")
         out["paper_benchmark"] = paper_leg(pr)
         progress("paper benchmark leg done")
+        out["three_asset"] = three_asset_leg(pr)
+        progress("three-asset leg done")
         if not args.no_fno:
             out["fno_coarse"] = fno_leg(pr, insts, seeds, serial_ref, args.fno_train_s)
             progress("fno leg done")
@@ -459,6 +492,9 @@ def paper_leg(pr, fine_spacings=(1.0, 0.5)):
     def rel(a, b):
         return float((a - b).abs().max() / b.abs().max())
 
+    def rel_l2(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
     def run(inst, kmax, kind=pr.PR_G_IMPLICIT, timed=()):
         """Serial F (timed on its second call), then Parareal with coarse
         propagator `kind` and max_iters = K for K = 1..kmax: error against
@@ -472,7 +508,7 @@ def paper_leg(pr, fine_spacings=(1.0, 0.5)):
         torch.cuda.synchronize()
         t_f = time.perf_counter() - t
         sref = ser.value.clone()
-        errs, incs, ms = [], [], {}
+        errs, errs_l2, incs, ms = [], [], [], {}
         for k in range(1, kmax + 1):
             s2 = pr.Solver(inst, bc_kind=pr.PR_BC_EXACT, coarse_kind=kind, max_iters=k)
             r = s2.solve()
@@ -483,11 +519,12 @@ def paper_leg(pr, fine_spacings=(1.0, 0.5)):
                 torch.cuda.synchronize()
                 ms[k] = (time.perf_counter() - t) * 1e3
             errs.append(float("%.3g" % rel(r.value, sref)))
+            errs_l2.append(float("%.3g" % rel_l2(r.value, sref)))
             incs.append(float("%.3g" % r.increments[-1]))
             s2.close()
         progress("paper leg: M=%d N=%d r=%g s1=%g s2=%g G=%d done" % (
             inst.M, inst.n_slices, inst.r, inst.sigma1, inst.sigma2, kind))
-        return sv, sref, t_f, errs, incs, ser.stats, ms
+        return sv, sref, t_f, (errs, errs_l2), incs, ser.stats, ms
 
     out = {"workload": "cash-or-nothing, [0,300]^2 spacing 1 (301^2), K1=K2=100, r=1, "
                        "sigma=0.3/0.3, rho=0.5, T=1, c=1; implicit F 3 steps/slice, implicit G "
@@ -544,8 +581,8 @@ def paper_leg(pr, fine_spacings=(1.0, 0.5)):
                "speedup_bound_K2": round(bound(cg, cf, 2), 3),
                "parareal_ms": {str(k): round(v, 2) for k, v in ms.items()},
                "speedup_vs_serial_f": {str(k): round(t_f * 1e3 / v, 3) for k, v in ms.items()},
-               "convergence": {"K": list(range(1, P + 1)), "err_vs_serial_f": errs,
-                               "last_increment": incs}}
+               "convergence": {"K": list(range(1, P + 1)), "err_vs_serial_f": errs[0],
+                               "rel_l2_vs_serial_f": errs[1], "last_increment": incs}}
         if kind == pr.PR_G_IMPLICIT:
             ref = golden_oracle("paper_serial_g_301.npy")
             if ref is not None and ref.shape == tuple(ug.shape):
@@ -559,17 +596,67 @@ def paper_leg(pr, fine_spacings=(1.0, 0.5)):
                              coarse_steps_per_slice=5)
         s_, _, tf, e, _, _, _ = run(ri, N, pr.PR_G_LOD)
         s_.close()
-        res.append({"spacing": spacing, "grid": ri.M, "N": N, "err_vs_serial_f": e,
-                    "serial_f_s": round(tf, 3)})
+        res.append({"spacing": spacing, "grid": ri.M, "N": N, "err_vs_serial_f": e[0],
+                    "rel_l2_vs_serial_f": e[1], "serial_f_s": round(tf, 3)})
     out["resolution_lod_g"] = res
     par = []
     for kw in (dict(r=0.1), dict(r=5.0), dict(sigma1=0.1), dict(sigma1=3.0), dict(sigma2=5.0)):
         ri = paper_benchmark(**kw)
         s_, _, _, e, _, _, _ = run(ri, ri.n_slices, pr.PR_G_LOD)
         s_.close()
-        k8 = next((k + 1 for k, x in enumerate(e) if x < 1e-8), None)
-        par.append(dict(kw, err_vs_serial_f=e, K_to_1e_8=k8))
+        k8 = next((k + 1 for k, x in enumerate(e[0]) if x < 1e-8), None)
+        par.append(dict(kw, err_vs_serial_f=e[0], rel_l2_vs_serial_f=e[1], K_to_1e_8=k8))
     out["parameters_lod_g"] = par
+    # the slice count of the paper's convergence figure (Sec. 4.1): 12 slices of
+    # 1/12, one implicit G step and three implicit F steps per slice
+    p12 = paper_benchmark(n_slices=12)
+    s_, _, _, e, incs12, _, _ = run(p12, 6, pr.PR_G_IMPLICIT)
+    s_.close()
+    out["convergence_P12_implicit_g"] = {"K": list(range(1, 7)), "err_vs_serial_f": e[0],
+                                         "rel_l2_vs_serial_f": e[1], "last_increment": incs12}
+    return out
+
+
+def three_asset_leg(pr):
+    """The three-asset generalisation (Eq. (bse_general), n = 3; 19-point
+    explicit scheme, FP64): Parareal on 65^3 with N = 16 and G on 17^3 against
+    the GPU's serial F, and the step kernel's throughput over all 16 slices at
+    65^3 and 129^3 (16 B of HBM per interior point-step: one read, one write;
+    49 FP64 operations: 7 for the i-dependent coefficients, 8 per axis, 5 per
+    pair, 1 for the reaction, 2 for the update)."""
+    import torch
+    from paper_2404_02521_amd import nasset
+    from synthetic import three_asset
+    out = {"workload": "basket call on three assets, seed 0 parameters, [0,4]^3, T=1, N=16, "
+                       "explicit F at 0.9 of the Gershgorin bound, G on a 4x coarser grid"}
+    inst = three_asset(0, M=65, coarse_M=17, n_slices=16).replace(tol=1e-8)
+    s = nasset.Solver3(inst)
+    ser, sst = s.serial_fine()
+    ser, sst = s.serial_fine()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    v, st = s.solve()
+    torch.cuda.synchronize()
+    t_par = time.perf_counter() - t
+    out["65^3_parareal"] = {
+        "fine_steps": st["fine_steps"], "coarse_steps": st["coarse_steps"], "iters": st["iters"],
+        "err_vs_serial_f": float((v - ser).abs().max() / ser.abs().max()),
+        "serial_f_ms": round(sst["t_total_ms"], 2), "parareal_ms": round(t_par * 1e3, 2),
+        "increments": [float("%.3g" % x) for x in st["increments"]]}
+    s.close()
+    for M, Mc in ((65, 17), (129, 33)):
+        pi = three_asset(0, M=M, coarse_M=Mc, n_slices=16)
+        sp = nasset.Solver3(pi)
+        sp.sweep_probe()
+        ms, ps = sp.sweep_probe()
+        sp.close()
+        rate = ps / (ms * 1e-3)
+        out["%d^3_sweep" % M] = {"slices": 16, "point_steps": ps, "ms": round(ms, 3),
+                                 "point_steps_per_s": round(rate, 1),
+                                 "effective_gbs": round(rate * 16 / 1e9, 1),
+                                 "hbm_frac_algorithmic": round(rate * 16 / 1e9 / HBM_PEAK_GBS, 4),
+                                 "fp64_tflops": round(rate * 49 / 1e12, 3)}
+        torch.cuda.empty_cache()
     return out
 
 
@@ -752,6 +839,25 @@ def serving_leg(pr, count=120, seed=11, sides=(129, 257)):
                                   "peak_resident": r["peak_resident"],
                                   "peak_arena_gb": round(r["peak_arena_bytes"] / 2 ** 30, 2)}
     sv.close()
+    # the survey's offered loads on the full mix, for one second of arrivals each,
+    # with load shedding: at most 16 requests wait (PR_EBUSY beyond), 16 resident
+    rates = {}
+    for rate in (50.0, 2000.0):
+        t, insts_r = serving_requests(rate, int(rate), seed=seed + 2,
+                                      sides=(129, 257, 513, 1025))
+        sq = Server(64 << 30, max_resident=16, n_streams=8, max_queued=16)
+        r = run_poisson(sq, t, insts_r)
+        row = {"offered_per_s": rate, "arrivals": int(rate), "served": r["served"],
+               "rejected": r["rejected"], "solves_per_s": round(r["solves_per_s"], 3)}
+        if r["served"]:
+            row.update(p50_ms=round(r["p50_ms"], 1), p99_ms=round(r["p99_ms"], 1),
+                       peak_resident=r["peak_resident"])
+        rates["%g_per_s" % rate] = row
+        sq.close()
+        progress("serving at %g req/s done" % rate)
+    out["offered_load_full_mix"] = dict(
+        rates, note="one second of Poisson arrivals per rate; queue bound 16 (refused beyond), "
+                    "16 resident; latency of the served requests, arrival to result")
     torch.cuda.empty_cache()
     return out
 

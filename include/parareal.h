@@ -54,7 +54,8 @@ typedef enum {
     PR_EDEVICE = 4,      /* a HIP runtime call failed */
     PR_ENOTCONV = 5,     /* max_iters reached above tolerance (result still written) */
     PR_ENONFINITE = 6,   /* a non-finite value appeared in the iteration */
-    PR_EMODEL = 7        /* coarse model unavailable */
+    PR_EMODEL = 7,       /* coarse model unavailable */
+    PR_EBUSY = 8         /* pr_server_submit: the bounded queue of waiting requests is full */
 } pr_status;
 
 /* Payoff at maturity (tau = 0). */
@@ -114,6 +115,19 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
  * increments grow (a non-finite increment then ends the solve with
  * PR_ENONFINITE, as for the other propagators). */
 #define PR_FLAG_NO_FALLBACK 4u
+/* PR_FLAG_SERIAL_CHAIN: run each iteration's coarse chain and correction after
+ * its whole fine sweep, on the solver's stream.  By default (explicit F with the
+ * numerical G, no PR_FLAG_GRAPH) an iteration with more than 32 active slices
+ * is split into two groups of consecutive slices (the first 32 or half, the
+ * rest): the fine sweep runs group by group on the solver's stream, and each
+ * group's gather, chain and correction run on a second stream of the solver as
+ * soon as its sweep ends, so the chain of one group overlaps the sweep of the
+ * next (the chain of a later group restarts from the corrected state at its
+ * first slice, which equals the chain's own value there bitwise).  Results are
+ * bitwise the same either way.  The phase timings then read: t_fine_ms the
+ * fine sweeps, t_chain_ms the chain and correction time left after the last
+ * sweep (the exposed part), t_correct_ms 0. */
+#define PR_FLAG_SERIAL_CHAIN 8u
 
 /* Time stepping of the fine propagator F.  PR_FINE_EXPLICIT: explicit Euler
  * (the planner keeps dt below the stability bound).  PR_FINE_IMPLICIT: implicit
@@ -312,7 +326,9 @@ typedef struct {
     int32_t max_resident; /* cap on resident requests (>= 1) */
     int32_t n_streams;    /* HIP streams shared by resident requests (1..32) */
     uint32_t flags;       /* reserved, 0 */
-    int32_t pad_;
+    int32_t max_queued;   /* waiting (submitted, not yet admitted) requests held at
+                             once; 0 = no bound.  Beyond it pr_server_submit
+                             refuses the request with PR_EBUSY (load shedding). */
 } pr_server_options;
 
 typedef struct {
@@ -331,7 +347,9 @@ pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_op
                            pr_server** out);
 /* Queue one solve; v_out: device pointer to n*n doubles, written when the request
  * completes.  Arguments are validated here (PR_EINVAL / PR_EUNSTABLE); a request
- * larger than the whole arena is rejected with PR_ENOMEM.  *id_out identifies it. */
+ * larger than the whole arena is rejected with PR_ENOMEM, and a request that
+ * finds max_queued requests already waiting with PR_EBUSY (nothing is queued;
+ * pr_server_rejected counts these refusals).  *id_out identifies it. */
 pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* model,
                            const pr_payoff* payoff, const pr_options* opt, double* v_out,
                            int64_t* id_out);
@@ -342,6 +360,8 @@ pr_status pr_server_progress(pr_server* sv, int32_t* n_resident, int32_t* n_queu
 pr_status pr_server_poll(pr_server* sv, int64_t id, int32_t* done, pr_request_info* info);
 /* Peak resident requests and peak arena bytes in use since creation. */
 pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t* peak_bytes);
+/* Submissions refused with PR_EBUSY since creation. */
+pr_status pr_server_rejected(const pr_server* sv, int64_t* n_rejected);
 /* Blocks until all submitted work has drained, then releases the streams. */
 pr_status pr_server_destroy(pr_server* sv);
 

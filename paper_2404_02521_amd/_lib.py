@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libparareal.so")
 PR_MAX_SLICES = 1024
 PR_STATIC_SCRATCH_BYTES = 64 << 20
 
-PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_ENOTCONV, PR_ENONFINITE, PR_EMODEL = range(8)
+(PR_OK, PR_EINVAL, PR_EUNSTABLE, PR_ENOMEM, PR_EDEVICE, PR_ENOTCONV, PR_ENONFINITE, PR_EMODEL,
+ PR_EBUSY) = range(9)
 PR_PAYOFF_BASKET_CALL, PR_PAYOFF_EXCHANGE, PR_PAYOFF_CASH_OR_NOTHING = 0, 1, 2
 PR_BC_FORWARD_INTRINSIC, PR_BC_DISCOUNTED_PAYOFF, PR_BC_EXACT = 0, 1, 2
 PR_G_NUMERICAL, PR_G_FNO, PR_G_FINE, PR_G_LOD, PR_G_IMPLICIT = 0, 1, 2, 3, 4
@@ -25,6 +26,7 @@ PR_OP_FINE, PR_OP_COARSE = 0, 1
 PR_FLAG_TIME_STEPS = 1
 PR_FLAG_GRAPH = 2
 PR_FLAG_NO_FALLBACK = 4
+PR_FLAG_SERIAL_CHAIN = 8
 PR_FNO_FP32, PR_FNO_BF16 = 0, 1
 PR_FNO_BASE_ZERO, PR_FNO_BASE_IDENTITY, PR_FNO_BASE_LOD, PR_FNO_BASE_FINE_LOD = 0, 1, 2, 3
 PR_FNO_GRID = 64
@@ -70,7 +72,7 @@ class pr_stats(C.Structure):
 
 class pr_server_options(C.Structure):
     _fields_ = [("max_resident", C.c_int32), ("n_streams", C.c_int32), ("flags", C.c_uint32),
-                ("pad_", C.c_int32)]
+                ("max_queued", C.c_int32)]
 
 
 class pr_fno_config(C.Structure):
@@ -91,6 +93,22 @@ class pr_request_info(C.Structure):
 
 
 # (name, restype, argtypes) of every exported entry point of include/parareal.h
+class pr3_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("coarse_n", C.c_int32), ("n_slices", C.c_int32),
+                ("max_iters", C.c_int32), ("fine_steps", C.c_int32), ("coarse_steps", C.c_int32),
+                ("s_max", C.c_double), ("T", C.c_double), ("tol", C.c_double),
+                ("cfl", C.c_double), ("sigma", C.c_double * 3), ("rho", C.c_double * 3),
+                ("r", C.c_double), ("w", C.c_double * 3), ("strike", C.c_double)]
+
+
+class pr3_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("fine_steps", C.c_int32), ("coarse_steps", C.c_int32),
+                ("pad_", C.c_int32), ("last_increment", C.c_double),
+                ("increments", C.c_double * (PR_MAX_SLICES + 1)), ("t_fine_ms", C.c_double),
+                ("t_coarse_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("fine_point_steps", C.c_int64)]
+
+
 SIGNATURES = [
     ("parareal_plan", C.c_int, [C.POINTER(pr_grid), C.POINTER(pr_model), C.POINTER(pr_options),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -124,6 +142,7 @@ SIGNATURES = [
     ("pr_server_poll", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
                                  C.POINTER(pr_request_info)]),
     ("pr_server_peaks", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
+    ("pr_server_rejected", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("pr_server_destroy", C.c_int, [C.c_void_p]),
     ("pr_fno_param_count", C.c_uint64, []),
     ("pr_fno_workspace_bytes", C.c_uint64, [C.c_int32]),
@@ -147,6 +166,15 @@ SIGNATURES = [
     ("pr_fno_load", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(pr_fno_file_info)]),
     ("pr_fno_destroy", C.c_int, [C.c_void_p]),
     ("pr_fno_last_error", C.c_char_p, [C.c_void_p]),
+    ("pr3_plan", C.c_int, [C.POINTER(pr3_problem), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("pr3_workspace_bytes", C.c_uint64, [C.POINTER(pr3_problem)]),
+    ("pr3_create", C.c_int, [C.POINTER(pr3_problem), C.c_void_p, C.c_uint64, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    ("pr3_solve", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(pr3_stats)]),
+    ("pr3_serial_fine", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(pr3_stats)]),
+    ("pr3_fine_sweep_probe", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("pr3_destroy", C.c_int, [C.c_void_p]),
+    ("pr3_last_error", C.c_char_p, [C.c_void_p]),
 ]
 
 _lib = None

@@ -281,6 +281,16 @@ struct pr_solver {
     double sweep_bytes = 0;            // their algorithmic bytes
     bool graph = false;                // PR_FLAG_GRAPH
     hipStream_t cap_stream = nullptr;  // capture vehicle (never executes work)
+    // overlapped chain (see PR_FLAG_SERIAL_CHAIN): second stream, one event per
+    // slice group plus the join, group count and smallest group
+    bool pipe = false;
+    hipStream_t chain_stream = nullptr;
+    static constexpr int kPipeMaxGroups = 8;
+    hipEvent_t pipe_ev[kPipeMaxGroups + 1]{};
+    int pipe_groups = 2;               // PR_PIPE_GROUPS (1..8; 1 = off)
+    int pipe_min = 32;                 // PR_PIPE_MIN: fewest slices per group
+    int pipe_min_rows = 48;            // PR_PIPE_MINROWS: shortest row chunk of a grouped sweep
+    bool bracket_sweep = true;         // fine_sweep records ev[4] / ev[5] itself
     std::map<int, hipGraphExec_t> graphs;   // key -1: initial sweep, k: iteration k
     std::map<int, hipGraph_t> graph_defs;
     std::string err;
@@ -426,7 +436,7 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         float* Lb = s->at<float>(tmp ? s->L.tLb : s->L.Lb) + off;
         StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
         HIPCHK(launch_fine_prep(Ubase + (long long)first * g.stride, Lb, A, a, s->stream));
-        if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+        if (step_ms && s->events && s->bracket_sweep) HIPCHK(hipEventRecord(s->ev[4], s->stream));
         for (int q = 1; q < s->mF;) {
             const int S = std::min(fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
@@ -446,14 +456,12 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
             std::swap(A, B);
             q += S;
         }
-        if (step_ms && s->events) {
-            HIPCHK(hipEventRecord(s->ev[5], s->stream));
-        }
+        if (step_ms && s->events && s->bracket_sweep) HIPCHK(hipEventRecord(s->ev[5], s->stream));
         *dres = A - off;
     } else {
         double* A = s->at<double>(tmp ? s->L.twA : s->L.wA) + off;
         double* B = s->at<double>(tmp ? s->L.twB : s->L.wB) + off;
-        if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+        if (step_ms && s->events && s->bracket_sweep) HIPCHK(hipEventRecord(s->ev[4], s->stream));
         for (int q = 0; q < s->mF;) {
             const int S = std::min(fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
@@ -474,7 +482,7 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
             if (q > 0) std::swap(A, B);
             q += S;
         }
-        if (step_ms && s->events) HIPCHK(hipEventRecord(s->ev[5], s->stream));
+        if (step_ms && s->events && s->bracket_sweep) HIPCHK(hipEventRecord(s->ev[5], s->stream));
         *wres = A - off;
     }
     return PR_OK;
@@ -732,12 +740,84 @@ pr_status init_phase(pr_solver* s, double* Ucur, double* Unext) {
     return PR_OK;
 }
 
+// Iteration k with the chain overlapped (numerical G, explicit F): slices
+// k..N-1 in G groups of gs consecutive slices.  Per group, on the solver's
+// stream: the fine sweep; on the chain stream, once that sweep has ended: the
+// gather of F at the coincident nodes, the chain over the group (the first
+// group starts from U^k_k, a later one from the corrected U^{k+1} at its first
+// slice, which the previous group's correction has written) and the correction
+// + norm of the group.  The chain of group g thus runs while group g+1 is swept.
+// The two streams touch disjoint slices of every buffer they share (F results,
+// Lb, foldc, Gold, dcor, U), except the chain's own scratch, which only the
+// chain stream uses.  The solver's stream waits for the chain stream at the
+// end, so callers see one stream-ordered phase.
+pr_status iteration_phase_overlapped(pr_solver* s, int k, double* Ucur, double* Unext,
+                                     double* step_ms, int gs, int G) {
+    const Grid& g = s->fg;
+    const int N = s->N;
+    const bool ev = step_ms != nullptr && s->events;
+    hipStream_t cs = s->chain_stream;
+    unsigned long long* red = s->red();
+    HIPCHK(launch_zero_red(red, s->stream));
+    if (k > 0)
+        HIPCHK(hipMemcpyAsync(Unext + (long long)k * g.stride, Ucur + (long long)k * g.stride,
+                              (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (ev) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+    // a group's launches have 1/G of the wavefronts; longer row chunks keep
+    // the temporally blocked kernel's recomputed halo rows a small share
+    struct Restore {   // the sweep settings come back on every return
+        pr_solver* s;
+        int min_rows;
+        ~Restore() {
+            s->min_rows = min_rows;
+            s->bracket_sweep = true;
+        }
+    } restore{s, s->min_rows};
+    s->min_rows = std::max(restore.min_rows, s->pipe_min_rows);
+    s->bracket_sweep = false;
+    for (int gi = 0; gi < G; ++gi) {
+        const int b0 = k + gi * gs, b1 = std::min(N, b0 + gs);
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, Ucur, b0, b1 - b0, false, &d, &w, step_ms);
+        if (r != PR_OK) return r;
+        const void* Fold = s->fp32 ? (const void*)d : (const void*)w;
+        HIPCHK(hipEventRecord(s->pipe_ev[gi], s->stream));
+        HIPCHK(hipStreamWaitEvent(cs, s->pipe_ev[gi], 0));
+        HIPCHK(launch_gather_coincident(Ucur, Fold, s->at<double>(s->L.foldc), g, s->nc, s->q, b0,
+                                        b1, s->fp32 ? 1 : 0, cs));
+        ChainArgs ca = chain_args(s, b0, b1, 0);
+        HIPCHK(launch_chain(gi == 0 ? Ucur : Unext, s->at<double>(s->L.Gold),
+                            s->at<double>(s->L.dcor), s->at<double>(s->L.cst),
+                            s->at<float>(s->L.lbc), ca, cs));
+        HIPCHK(launch_correct(Ucur, Fold, s->at<double>(s->L.dcor), nullptr, nullptr, Unext, red,
+                              g, b0, b1, N, s->nc, s->q, s->fp32, 0, cs));
+    }
+    if (ev) {
+        HIPCHK(hipEventRecord(s->ev[5], s->stream));
+        HIPCHK(hipEventRecord(s->ev[1], s->stream));
+    }
+    HIPCHK(hipEventRecord(s->pipe_ev[G], cs));
+    HIPCHK(hipStreamWaitEvent(s->stream, s->pipe_ev[G], 0));
+    if (ev) {
+        HIPCHK(hipEventRecord(s->ev[2], s->stream));
+        HIPCHK(hipEventRecord(s->ev[3], s->stream));
+    }
+    return PR_OK;
+}
+
 // Iteration k: F sweep over slices k..N-1, coarse chain, correction + norm
 // into Unext (stream-ordered, no host sync).  step_ms != nullptr enables the
 // per-phase and per-launch timing events.
 pr_status iteration_phase(pr_solver* s, int k, double* Ucur, double* Unext, double* step_ms) {
     const Grid& g = s->fg;
     const int N = s->N;
+    if (s->pipe && !s->fineg && !s->implicit) {
+        const int active = N - k;
+        const int gs = std::max(s->pipe_min, (active + s->pipe_groups - 1) / s->pipe_groups);
+        const int G = (active + gs - 1) / gs;
+        if (G > 1) return iteration_phase_overlapped(s, k, Ucur, Unext, step_ms, gs, G);
+    }
     const float* d = nullptr;
     const double* w = nullptr;
     const bool ev = step_ms != nullptr && s->events;
@@ -961,6 +1041,7 @@ const char* parareal_strerror(pr_status st) {
         case PR_ENOTCONV: return "not converged within max_iters";
         case PR_ENONFINITE: return "non-finite value";
         case PR_EMODEL: return "coarse model unavailable";
+        case PR_EBUSY: return "request queue full";
     }
     return "unknown status";
 }
@@ -1091,6 +1172,10 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_TIME_EVERY")) s->ev_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_MINROWS")) s->min_rows = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("PR_PIPE_GROUPS"))
+        s->pipe_groups = std::max(1, std::min(pr_solver::kPipeMaxGroups, std::atoi(e)));
+    if (const char* e = std::getenv("PR_PIPE_MIN")) s->pipe_min = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("PR_PIPE_MINROWS")) s->pipe_min_rows = std::max(1, std::atoi(e));
     if (!s->fineg && chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0)) != hipSuccess)
         return PR_EDEVICE;
     if ((s->lod || s->fnog) && lod_set_lds(s->fg.nin) != hipSuccess) return PR_EDEVICE;
@@ -1112,6 +1197,13 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     s->graph = (opt->flags & PR_FLAG_GRAPH) != 0;
     if (s->graph && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return PR_EDEVICE;
+    if (!s->graph && !(opt->flags & PR_FLAG_SERIAL_CHAIN) && !s->implicit && s->pipe_groups > 1 &&
+        hipStreamCreateWithFlags(&s->chain_stream, hipStreamNonBlocking) == hipSuccess) {
+        bool eok = true;
+        for (int i = 0; i <= s->pipe_groups; ++i)
+            eok = eok && hipEventCreateWithFlags(&s->pipe_ev[i], hipEventDisableTiming) == hipSuccess;
+        s->pipe = eok;   // otherwise the chain stays serial (the objects are released later)
+    }
     if ((opt->flags & PR_FLAG_TIME_STEPS) && !s->graph) {
         s->step_ev.resize(2 * (size_t)mf, nullptr);
         for (auto& e : s->step_ev)
@@ -1136,6 +1228,9 @@ void release_runtime_objects(pr_solver* s) {
     for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : s->graph_defs) (void)hipGraphDestroy(kv.second);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    for (auto& e : s->pipe_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->chain_stream) (void)hipStreamDestroy(s->chain_stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1456,6 +1551,8 @@ struct pr_server {
     std::vector<int64_t> resident;
     int64_t next_id = 1;
     int max_resident = 1, rr = 0, peak_resident = 0, n_done = 0;
+    int max_queued = 0;                   // 0: no bound on waiting requests
+    int64_t n_rejected = 0;               // submissions refused with PR_EBUSY
     uint64_t used = 0, peak_bytes = 0;
 };
 
@@ -1512,6 +1609,9 @@ pr_status req_admit(pr_server* sv, Req& r) {
     const int si = sv->rr++ % (int)sv->streams.size();
     pr_options o = r.o;
     o.flags &= ~(PR_FLAG_GRAPH | PR_FLAG_TIME_STEPS);
+    // requests already overlap across the server's streams: no per-request
+    // chain stream (it would be created and destroyed at every admission)
+    o.flags |= PR_FLAG_SERIAL_CHAIN;
     pr_status st = parareal_create(&r.g, &r.m, &r.p, &o, sv->arena + r.off, r.bytes,
                                    sv->streams[si], &r.s);
     if (st != PR_OK) return st;
@@ -1576,13 +1676,15 @@ pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_op
     if (!out || !arena || !opt) return PR_EINVAL;
     *out = nullptr;
     if (reinterpret_cast<uintptr_t>(arena) % kAlign) return PR_EINVAL;
-    if (opt->max_resident < 1 || opt->n_streams < 1 || opt->n_streams > 32) return PR_EINVAL;
+    if (opt->max_resident < 1 || opt->n_streams < 1 || opt->n_streams > 32 || opt->max_queued < 0)
+        return PR_EINVAL;
     pr_server* sv = new (std::nothrow) pr_server();
     if (!sv) return PR_ENOMEM;
     sv->arena = reinterpret_cast<char*>(arena);
     sv->arena_bytes = arena_bytes / kAlign * kAlign;
     sv->free_[0] = sv->arena_bytes;
     sv->max_resident = opt->max_resident;
+    sv->max_queued = opt->max_queued;
     for (int i = 0; i < opt->n_streams; ++i) {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -1622,6 +1724,10 @@ pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* m
     r.bytes = pr_server_footprint(grid, opt);
     if (r.bytes == 0) return PR_EINVAL;
     if (r.bytes > sv->arena_bytes) return PR_ENOMEM;
+    if (sv->max_queued > 0 && (int)sv->queue.size() >= sv->max_queued) {
+        sv->n_rejected += 1;
+        return PR_EBUSY;
+    }
     r.t_submit = std::chrono::steady_clock::now();
     *id_out = r.id;
     sv->queue.push_back(r.id);
@@ -1709,6 +1815,12 @@ pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t*
     if (!sv) return PR_EINVAL;
     if (peak_resident) *peak_resident = sv->peak_resident;
     if (peak_bytes) *peak_bytes = sv->peak_bytes;
+    return PR_OK;
+}
+
+pr_status pr_server_rejected(const pr_server* sv, int64_t* n_rejected) {
+    if (!sv || !n_rejected) return PR_EINVAL;
+    *n_rejected = sv->n_rejected;
     return PR_OK;
 }
 

@@ -18,12 +18,12 @@ from .parareal import make_structs
 
 class Server:
     def __init__(self, arena_bytes: int, max_resident: int = 64, n_streams: int = 4,
-                 device=None):
+                 device=None, max_queued: int = 0):
         import torch
         self.device = torch.device(device or "cuda")
         self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
         ptr = (self._arena.data_ptr() + 255) // 256 * 256
-        o = L.pr_server_options(max_resident, n_streams, 0, 0)
+        o = L.pr_server_options(max_resident, n_streams, 0, max_queued)
         h = C.c_void_p()
         L.check(L.lib().pr_server_create(C.c_void_p(ptr), C.c_uint64(int(arena_bytes)),
                                          C.byref(o), C.byref(h)), "pr_server_create")
@@ -35,16 +35,25 @@ class Server:
         g, _, _, o = make_structs(inst, coarse_kind)
         return int(L.lib().pr_server_footprint(C.byref(g), C.byref(o)))
 
-    def submit(self, inst, coarse_kind: int = L.PR_G_LOD, max_iters: int = 0) -> int:
+    def submit(self, inst, coarse_kind: int = L.PR_G_LOD, max_iters: int = 0):
+        """Queue a solve; returns its id, or None when the bounded queue refused
+        it (PR_EBUSY)."""
         import torch
         g, m, p, o = make_structs(inst, coarse_kind, max_iters)
         out = torch.empty((inst.M, inst.M), dtype=torch.float64, device=self.device)
         rid = C.c_int64()
-        L.check(L.lib().pr_server_submit(self._h, C.byref(g), C.byref(m), C.byref(p), C.byref(o),
-                                         C.c_void_p(out.data_ptr()), C.byref(rid)),
-                "pr_server_submit")
+        st = L.lib().pr_server_submit(self._h, C.byref(g), C.byref(m), C.byref(p), C.byref(o),
+                                      C.c_void_p(out.data_ptr()), C.byref(rid))
+        if st == L.PR_EBUSY:
+            return None
+        L.check(st, "pr_server_submit")
         self._out[rid.value] = out
         return rid.value
+
+    def rejected(self) -> int:
+        n = C.c_int64()
+        L.check(L.lib().pr_server_rejected(self._h, C.byref(n)), "pr_server_rejected")
+        return n.value
 
     def progress(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
@@ -123,7 +132,8 @@ def run_poisson(server: Server, arrivals, instances, coarse_kind: int = L.PR_G_L
         while nxt < n and arrivals[nxt] <= now:
             rid = server.submit(instances[nxt], coarse_kind)
             ids[nxt] = rid
-            pending[rid] = nxt
+            if rid is not None:   # None: refused by the bounded queue
+                pending[rid] = nxt
             nxt += 1
         server.progress()
         for rid in list(pending):
@@ -140,10 +150,15 @@ def run_poisson(server: Server, arrivals, instances, coarse_kind: int = L.PR_G_L
             raise TimeoutError("Poisson run did not drain")
         if not pending and nxt < n:
             time.sleep(max(0.0, min(0.001, arrivals[nxt] - (time.perf_counter() - t0))))
-    lat = [(done_t[i] - arrivals[i]) * 1e3 for i in range(n)]
-    span = max(done_t) - arrivals[0]
-    return dict(count=n, solves_per_s=n / span, p50_ms=nearest_rank(lat, 50),
-                p99_ms=nearest_rank(lat, 99), mean_ms=sum(lat) / n, span_s=span,
-                iters=[x["iters"] for x in infos], statuses=[x["status"] for x in infos],
+    served = [i for i in range(n) if ids[i] is not None]
+    if not served:
+        return dict(count=n, served=0, rejected=n, solves_per_s=0.0, ids=ids)
+    lat = [(done_t[i] - arrivals[i]) * 1e3 for i in served]
+    span = max(done_t[i] for i in served) - arrivals[0]
+    return dict(count=n, served=len(served), rejected=n - len(served),
+                solves_per_s=len(served) / span, p50_ms=nearest_rank(lat, 50),
+                p99_ms=nearest_rank(lat, 99), mean_ms=sum(lat) / len(lat), span_s=span,
+                iters=[infos[i]["iters"] for i in served],
+                statuses=[infos[i]["status"] for i in served],
                 peak_resident=server.peaks()[0], peak_arena_bytes=server.peaks()[1],
                 ids=ids)

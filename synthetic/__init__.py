@@ -113,6 +113,49 @@ def paper_benchmark(n_slices: int = 10, fine_steps_per_slice: int = 3, spacing: 
     return Instance(**d)
 
 
+@dataclass(frozen=True)
+class Instance3:
+    """One three-asset pricing problem (Eq. (bse_general), n = 3) on an M^3 grid
+    over [0, s_max]^3, basket call max(w . S - K, 0); rho = (rho12, rho13, rho23)."""
+    M: int
+    coarse_M: int
+    sigma: tuple
+    rho: tuple
+    r: float
+    T: float
+    w: tuple
+    strike: float
+    n_slices: int = 8
+    s_max: float = 4.0
+    tol: float = 0.0
+    max_iters: int = 0
+    fine_steps: int = 0
+    coarse_steps: int = 0
+    cfl: float = 0.9
+
+    def replace(self, **kw) -> "Instance3":
+        return replace(self, **kw)
+
+
+def three_asset(seed: int, M: int = 65, coarse_M: int = 17, n_slices: int = 16,
+                T: float = 1.0) -> Instance3:
+    """sigma_d ~ U[0.1, 0.5]; (rho12, rho13, rho23) ~ U[-0.5, 0.5] each, drawn
+    again until the correlation matrix is positive definite; r ~ U[0, 0.1];
+    weights ~ Dirichlet(1, 1, 1); K ~ U[0.5, 1.5]."""
+    rng = np.random.default_rng(seed)
+    sigma = tuple(float(x) for x in rng.uniform(0.1, 0.5, size=3))
+    while True:
+        rho = tuple(float(x) for x in rng.uniform(-0.5, 0.5, size=3))
+        a, b, c = rho
+        if 1.0 - a * a - b * b - c * c + 2.0 * a * b * c > 0.0:
+            break
+    r = float(rng.uniform(0.0, 0.1))
+    w = tuple(float(x) for x in rng.dirichlet([1.0, 1.0, 1.0]))
+    K = float(rng.uniform(0.5, 1.5))
+    return Instance3(M=M, coarse_M=coarse_M, sigma=sigma, rho=rho, r=r, T=T, w=w, strike=K,
+                     n_slices=n_slices)
+
+
 SERVE_SIDES = (129, 257, 513, 1025)
 SERVE_SLICES = (16, 32, 64)
 

@@ -16,9 +16,12 @@ HEADER = os.path.join(ROOT, "include", "parareal.h")
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:parareal|pr_server|pr_fno)_\w+)\s*\(", src)))
+    """Every entry point declared in include/*.h."""
+    names = set()
+    for h in (HEADER, os.path.join(ROOT, "include", "parareal3.h")):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:parareal|pr_server|pr_fno|pr3)_\w+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -29,6 +32,30 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
     assert {n for n, _, _ in L.SIGNATURES} == set(names)
     assert lib.parareal_abi_version() == 2
+
+
+def test_constants_match_header(tmp_path):
+    """Every PR_* constant of the header (#define or enum) that the binding
+    mirrors has the value the C compiler gives it; the option flags, kinds and
+    status codes are all mirrored."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    names = set(re.findall(r"#define\s+(PR_[A-Z0-9_]+)\s", src))
+    names |= set(re.findall(r"\b(PR_[A-Z0-9_]+)\s*=", src))
+    names.discard("PR_H")
+    must = {n for n in names if re.match(r"PR_(FLAG|PAYOFF|BC|G|FINE|FP|OP|E|OK|FNO_BASE)", n)}
+    assert {"PR_FLAG_SERIAL_CHAIN", "PR_G_IMPLICIT", "PR_PAYOFF_CASH_OR_NOTHING"} <= must
+    for n in must:
+        assert hasattr(L, n), n
+    mirrored = sorted(n for n in names if hasattr(L, n))
+    body = "".join('printf("%%s %%lld\\n", "%s", (long long)(%s));' % (n, n) for n in mirrored)
+    c = tmp_path / "k.c"
+    c.write_text('#include <stdio.h>\n#include "%s"\nint main(void){%s return 0;}\n' % (HEADER, body))
+    exe = tmp_path / "k"
+    subprocess.run(["gcc", "-o", str(exe), str(c)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict(line.split() for line in out.strip().splitlines())
+    for n in mirrored:
+        assert int(got[n]) == int(getattr(L, n)), n
 
 
 def test_struct_layouts_match_header(tmp_path):

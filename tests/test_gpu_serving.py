@@ -1,11 +1,13 @@
 """Continuous-batching server: each result is the same alone and in the mix
-(bitwise: per-request kernels are deterministic and independent), admission
-respects the arena, failures are reported per request."""
+(bitwise: per-request kernels are deterministic and independent), served
+results match the FP64 oracle's serial F, admission respects the arena and the
+bounded queue, failures are reported per request."""
 import numpy as np
 import pytest
 
-from helpers import say
-from synthetic import plain_at_scale
+import oracle
+from helpers import oproblem, rel_max, say
+from synthetic import plain_at_scale, serving_requests
 
 pytestmark = pytest.mark.gpu
 
@@ -84,4 +86,49 @@ def test_rejects_and_statuses(pr):
     assert info["status"] == 5 and info["iters"] == 1   # PR_ENOTCONV, result still written
     alone = pr.Solver(small, coarse_kind=pr.PR_G_LOD, max_iters=1).solve()
     assert np.array_equal(host(sv.result(rid)), host(alone.value))
+    sv.close()
+
+
+def test_served_requests_vs_oracle(pr):
+    """Requests of the serving draw (129^2, N in {16, 32, 64}, T ~ U[0.25, 2],
+    FP32 F), served in a mix with LOD and numerical coarse propagators: each
+    result within 1e-5 relative of the oracle's FP64 serial F (the Parareal
+    stop is 1e-7 relative)."""
+    from paper_2404_02521_amd.serve import Server
+    _, insts = serving_requests(1.0, 4, seed=21, sides=(129,))
+    kinds = [pr.PR_G_LOD, pr.PR_G_NUMERICAL, pr.PR_G_LOD, pr.PR_G_NUMERICAL]
+    say("served vs oracle", [(i.n_slices, round(i.T, 3)) for i in insts])
+    sv = Server(4 << 30, max_resident=4, n_streams=2)
+    ids = [sv.submit(inst, k) for inst, k in zip(insts, kinds)]
+    infos = sv.drain(ids, timeout_s=300)
+    for rid, inst in zip(ids, insts):
+        assert infos[rid]["status"] == 0
+        mf, _, _, _ = pr.plan(inst)
+        ref = oracle.serial_fine(oproblem(inst), inst.n_slices, inst.T, mf)
+        err = rel_max(host(sv.result(rid)), ref)
+        print("N", inst.n_slices, "T %.3f" % inst.T, "K", infos[rid]["iters"], "err %.2e" % err)
+        assert err <= 1e-5
+    sv.close()
+
+
+def test_bounded_queue_refuses_and_recovers(pr):
+    """max_queued = 2: of six submissions made before the scheduler runs, two
+    wait and four are refused with PR_EBUSY (counted); the two served results
+    equal their solves alone, and after the drain the queue accepts again."""
+    from paper_2404_02521_amd.serve import Server
+    reqs = [plain_at_scale(400 + k, M=65, n_slices=8, coarse_M=33) for k in range(6)]
+    say("bounded queue")
+    sv = Server(1 << 30, max_resident=1, n_streams=1, max_queued=2)
+    ids = [sv.submit(inst) for inst in reqs]
+    assert [i is not None for i in ids] == [True, True, False, False, False, False]
+    assert sv.rejected() == 4
+    infos = sv.drain([i for i in ids if i is not None], timeout_s=120)
+    for rid, inst in zip(ids[:2], reqs[:2]):
+        assert infos[rid]["status"] == 0
+        alone = pr.Solver(inst, coarse_kind=pr.PR_G_LOD).solve()
+        assert np.array_equal(host(sv.result(rid)), host(alone.value))
+    rid = sv.submit(reqs[2])
+    assert rid is not None
+    assert sv.drain([rid], timeout_s=120)[rid]["status"] == 0
+    assert sv.rejected() == 4
     sv.close()
