@@ -136,6 +136,10 @@ def main():
                     help="run only the 2049^2, 256-slice solve (LOD G) against serial F")
     ap.add_argument("--paper-only", action="store_true",
                     help="run only the paper's cash-or-nothing benchmark leg")
+    ap.add_argument("--three-asset-probe", default=None,
+                    help="M,N: one three-asset fine sweep over N slices of M^3 (profiling)")
+    ap.add_argument("--krylov-probe", action="store_true",
+                    help="one serial implicit F of the paper problem (profiling)")
     ap.add_argument("--three-asset-only", action="store_true",
                     help="run only the three-asset leg")
     ap.add_argument("--serving-only", action="store_true",
@@ -165,7 +169,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.largest_share_only or args.step_probe:
+    def copy_probe():
+        # a plain device-to-device copy of known size: the calibration of the
+        # FETCH_SIZE / WRITE_SIZE counters in the same process
         if args.copy_probe_mib:
             n = args.copy_probe_mib << 20
             src = torch.ones(n, dtype=torch.uint8, device=dev)
@@ -174,6 +180,32 @@ def main():
             dst.copy_(src)
             torch.cuda.synchronize()
             del src, dst
+
+    if args.three_asset_probe:
+        copy_probe()
+        from paper_2404_02521_amd import nasset
+        from synthetic import three_asset
+        M, N = (int(x) for x in args.three_asset_probe.split(","))
+        sp = nasset.Solver3(three_asset(0, M=M, coarse_M=(M - 1) // 4 + 1, n_slices=N))
+        sp.sweep_probe()
+        ms, ps = sp.sweep_probe()
+        sp.close()
+        print(json.dumps({"workload": "three-asset %d^3 x %d slices, one fine sweep" % (M, N),
+                          "point_steps": ps, "ms": ms, "point_steps_per_s": ps / (ms * 1e-3),
+                          "effective_gbs": ps * 16 / (ms * 1e-3) / 1e9}), flush=True)
+        return
+    if args.krylov_probe:
+        copy_probe()
+        from synthetic import paper_benchmark
+        sv = pr.Solver(paper_benchmark(), bc_kind=pr.PR_BC_EXACT, coarse_kind=pr.PR_G_IMPLICIT)
+        r = sv.serial_fine()
+        sv.close()
+        print(json.dumps({"workload": "paper problem 301^2, serial implicit F (30 steps)",
+                          "krylov_iters": r.stats["krylov_iters"],
+                          "ms": r.stats["t_total_ms"]}), flush=True)
+        return
+    if args.largest_share_only or args.step_probe:
+        copy_probe()
         if args.step_probe:
             M, N = (int(x) for x in args.step_probe.split(","))
             print(json.dumps(step_probe(pr, M, N)), flush=True)
