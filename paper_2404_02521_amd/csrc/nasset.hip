@@ -11,10 +11,12 @@
 //
 // Kernels:
 //   k3_step    : one explicit step of every active slice.  A workgroup owns a
-//                tile of 8 j-rows x 64 k-columns and marches along i over a
-//                chunk of planes with the planes i-1, i, i+1 of the tile (and
-//                its one-node halo) in an LDS ring: each plane is read from
-//                HBM once per tile and used by three output planes.
+//                tile of 16 j-rows x 64 k-columns (two rows per thread) and
+//                marches along i over a chunk of planes through a ring of four
+//                LDS planes (the tile and its one-node halo): each plane is
+//                read from HBM once per tile and serves three output planes;
+//                one barrier per plane, the next plane's loads in flight while
+//                a plane is computed.
 //   k3_restrict: injection of a fine state to the coarse interior.
 //   k3_correct : U_{n+1} = F_n + P(g_new - g_old) (trilinear P), or P(g) in
 //                the initial sweep, fused with the max-increment reduction.
@@ -25,6 +27,7 @@
 #include <cfloat>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -34,8 +37,8 @@
 namespace pr3 {
 
 constexpr int kTK = 64;                  // k columns per tile: one wavefront
-constexpr int kTJ = 8;                   // j rows per tile
-constexpr int kThreads = kTK * kTJ;      // 512
+constexpr int kThreads = 512;            // per workgroup: kTK x (TJ / RJ)
+constexpr int kSlots = 4;                // LDS ring of planes
 constexpr int kCorrBlock = 256;
 
 struct G3 {
@@ -70,10 +73,18 @@ struct Step3 {
     int ntk;             // k tiles
 };
 
+// TJ j-rows per tile, RJ rows per thread (rows tj, tj + TJ / RJ, ...).
+template <int TJ, int RJ>
 __global__ __launch_bounds__(kThreads) void k3_step(const double* __restrict__ in,
                                                     double* __restrict__ out, Step3 a) {
 #pragma clang fp contract(on)
-    __shared__ double pl[3][kTJ + 2][kTK + 2];
+    static_assert(kTK * TJ / RJ == kThreads, "tile shape and workgroup size disagree");
+    constexpr int kTJ = TJ, kRJ = RJ;
+    // A tile and its one-node halo: (kTJ + 2) x (kTK + 2) values per plane, at
+    // most kPer per thread (element e = threadIdx.x + t * kThreads).
+    constexpr int kTile = (kTJ + 2) * (kTK + 2);
+    constexpr int kPer = (kTile + kThreads - 1) / kThreads;
+    __shared__ double pl[kSlots][kTJ + 2][kTK + 2];
     const G3& g = a.g;
     const int tk = threadIdx.x % kTK, tj = threadIdx.x / kTK;
     const int kt = blockIdx.x % a.ntk, jt = blockIdx.x / a.ntk;
@@ -83,51 +94,95 @@ __global__ __launch_bounds__(kThreads) void k3_step(const double* __restrict__ i
     const double tau = (a.first + s) * a.dT + a.tq;
     const double disc = exp(-a.b.r * tau);
     const int i0 = 1 + blockIdx.y * a.rows, i1 = min(i0 + a.rows - 1, g.nin);
-    auto value = [&](int i, int j, int k) -> double {   // node (i, j, k) of the input
-        if (i <= 0 || i >= g.n - 1 || j <= 0 || j >= g.n - 1 || k <= 0 || k >= g.n - 1)
-            return face_value(a.b, i, j, k, disc);
-        return in[base + (long long)(i - 1) * g.plane + (long long)(j - 1) * g.pitch + (k - 1)];
-    };
-    auto load = [&](int i, int slot) {
-        for (int e = threadIdx.x; e < (kTJ + 2) * (kTK + 2); e += kThreads) {
-            const int dj = e / (kTK + 2), dk = e % (kTK + 2);
-            const int j = jb + dj, k = kb + dk;
-            pl[slot][dj][dk] = (j < g.n && k < g.n) ? value(i, j, k) : 0.0;   // past the grid: unused
+    // the halo elements this thread loads, mapped once: node (j, k), whether it
+    // lies on the grid and whether it is interior in j and k
+    int ej[kPer], ek[kPer];
+    long long eo[kPer];
+    bool eon[kPer], ein[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = threadIdx.x + t * kThreads;
+        ej[t] = jb + e / (kTK + 2);
+        ek[t] = kb + e % (kTK + 2);
+        eon[t] = e < kTile && ej[t] < g.n && ek[t] < g.n;   // past the grid: never read
+        ein[t] = ej[t] >= 1 && ej[t] <= g.nin && ek[t] >= 1 && ek[t] <= g.nin;
+        eo[t] = (long long)(ej[t] - 1) * g.pitch + (ek[t] - 1);
+    }
+    auto fetch = [&](int i, double* r) {   // plane i of the input, node values
+        const bool iin = i >= 1 && i <= g.nin;
+        const long long po = base + (long long)(i - 1) * g.plane;
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            r[t] = 0.0;
+            if (eon[t]) r[t] = (iin && ein[t]) ? in[po + eo[t]] : face_value(a.b, i, ej[t], ek[t], disc);
         }
     };
-    const int j = jb + 1 + tj, k = kb + 1 + tk;   // this thread's output node
-    const bool act = j <= g.nin && k <= g.nin;
-    const double kj = j, kk = k;
-    const double ay = a.c.a[1] * kj * kj, az = a.c.a[2] * kk * kk;
-    const double my = a.c.hr * kj, mz = a.c.hr * kk;
-    const double gyz = a.c.g[2] * kj * kk;
-    load(i0 - 1, 0);
-    load(i0, 1);
+    auto store = [&](int i, const double* r) {
+        double* slot = &pl[i & (kSlots - 1)][0][0];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int e = threadIdx.x + t * kThreads;
+            if (e < kTile) slot[e] = r[t];
+        }
+    };
+    const int k = kb + 1 + tk;   // this thread's output column and rows
+    int j[kRJ];
+    bool act[kRJ];
+    double kj[kRJ], ay[kRJ], my[kRJ], gyz[kRJ];
+    const double kk = k, az = a.c.a[2] * kk * kk, mz = a.c.hr * kk;
+#pragma unroll
+    for (int q = 0; q < kRJ; ++q) {
+        j[q] = jb + 1 + tj + q * (kTJ / kRJ);
+        act[q] = j[q] <= g.nin && k <= g.nin;
+        kj[q] = j[q];
+        ay[q] = a.c.a[1] * kj[q] * kj[q];
+        my[q] = a.c.hr * kj[q];
+        gyz[q] = a.c.g[2] * kj[q] * kk;
+    }
+    // Ring of four planes, one barrier per plane: while plane i is computed
+    // from planes i-1, i, i+1, plane i+2 goes into the fourth slot (its last
+    // reader, plane i-1's computation, ended before this plane's barrier) and
+    // the loads of plane i+3 are in flight.
+    double nxt[kPer];
+    fetch(i0 - 1, nxt);
+    store(i0 - 1, nxt);
+    fetch(i0, nxt);
+    store(i0, nxt);
+    fetch(i0 + 1, nxt);
+    store(i0 + 1, nxt);
+    if (i0 + 1 <= i1) fetch(i0 + 2, nxt);
     for (int i = i0; i <= i1; ++i) {
-        const int sm = (i - i0) % 3, sc = (i - i0 + 1) % 3, sp = (i - i0 + 2) % 3;
-        load(i + 1, sp);
         __syncthreads();
-        if (act) {
-            const double ki = i;
-            const double ax = a.c.a[0] * ki * ki, mx = a.c.hr * ki;
-            const double gxy = a.c.g[0] * ki * kj, gxz = a.c.g[1] * ki * kk;
-            const int y = tj + 1, z = tk + 1;
-            const double u = pl[sc][y][z];
-            const double xp = pl[sp][y][z], xm = pl[sm][y][z];
-            const double yp = pl[sc][y + 1][z], ym = pl[sc][y - 1][z];
-            const double zp = pl[sc][y][z + 1], zm = pl[sc][y][z - 1];
+        const double (*pm)[kTK + 2] = pl[(i - 1) & (kSlots - 1)];
+        const double (*pc)[kTK + 2] = pl[i & (kSlots - 1)];
+        const double (*pp)[kTK + 2] = pl[(i + 1) & (kSlots - 1)];
+        const double ki = i;
+        const double ax = a.c.a[0] * ki * ki, mx = a.c.hr * ki;
+        const double gxz = a.c.g[1] * ki * kk;
+        const int z = tk + 1;
+#pragma unroll
+        for (int q = 0; q < kRJ; ++q) {
+            if (!act[q]) continue;
+            const double gxy = a.c.g[0] * ki * kj[q];
+            const int y = tj + 1 + q * (kTJ / kRJ);
+            const double u = pc[y][z];
+            const double xp = pp[y][z], xm = pm[y][z];
+            const double yp = pc[y + 1][z], ym = pc[y - 1][z];
+            const double zp = pc[y][z + 1], zm = pc[y][z - 1];
             double L = -a.c.r * u;
             L += ax * (xp - 2.0 * u + xm) + mx * (xp - xm);
-            L += ay * (yp - 2.0 * u + ym) + my * (yp - ym);
+            L += ay[q] * (yp - 2.0 * u + ym) + my[q] * (yp - ym);
             L += az * (zp - 2.0 * u + zm) + mz * (zp - zm);
-            L += gxy * (pl[sp][y + 1][z] + pl[sm][y - 1][z] - pl[sp][y - 1][z] - pl[sm][y + 1][z]);
-            L += gxz * (pl[sp][y][z + 1] + pl[sm][y][z - 1] - pl[sp][y][z - 1] - pl[sm][y][z + 1]);
-            L += gyz * (pl[sc][y + 1][z + 1] + pl[sc][y - 1][z - 1] - pl[sc][y + 1][z - 1] -
-                        pl[sc][y - 1][z + 1]);
-            out[base + (long long)(i - 1) * g.plane + (long long)(j - 1) * g.pitch + (k - 1)] =
+            L += gxy * (pp[y + 1][z] + pm[y - 1][z] - pp[y - 1][z] - pm[y + 1][z]);
+            L += gxz * (pp[y][z + 1] + pm[y][z - 1] - pp[y][z - 1] - pm[y][z + 1]);
+            L += gyz[q] * (pc[y + 1][z + 1] + pc[y - 1][z - 1] - pc[y + 1][z - 1] - pc[y - 1][z + 1]);
+            out[base + (long long)(i - 1) * g.plane + (long long)(j[q] - 1) * g.pitch + (k - 1)] =
                 u + a.dt * L;
         }
-        __syncthreads();
+        if (i + 1 <= i1) {   // plane i + 2 is read by plane i + 1's computation
+            store(i + 2, nxt);
+            if (i + 2 <= i1) fetch(i + 3, nxt);
+        }
     }
 }
 
@@ -344,6 +399,7 @@ struct pr3_solver {
     hipStream_t st = nullptr;
     hipEvent_t ev[4]{};
     bool events = false;
+    int tile_rows = 16;   // j-rows per step tile: 8, 16 or 32 (PR3_TILE_ROWS)
     std::string err;
     template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
 };
@@ -379,14 +435,20 @@ pr_status sweep(pr3_solver* s, const G3& g, const C3& c, const B3& b, const doub
     a.dT = s->dT;
     a.first = first;
     a.ntk = (g.nin + kTK - 1) / kTK;
-    const int ntj = (g.nin + kTJ - 1) / kTJ;
+    const int TJ = s->tile_rows;
+    const int ntj = (g.nin + TJ - 1) / TJ;
     a.rows = step_rows(g, a.ntk * ntj, count);
     const dim3 grid(a.ntk * ntj, (g.nin + a.rows - 1) / a.rows, count);
     const double* src = in;
     double* dst = A;
     for (int q = 0; q < m; ++q) {
         a.tq = q * dt;
-        hipLaunchKernelGGL(k3_step, grid, dim3(kThreads), 0, s->st, src, dst, a);
+        if (TJ == 32)
+            hipLaunchKernelGGL((k3_step<32, 4>), grid, dim3(kThreads), 0, s->st, src, dst, a);
+        else if (TJ == 8)
+            hipLaunchKernelGGL((k3_step<8, 1>), grid, dim3(kThreads), 0, s->st, src, dst, a);
+        else
+            hipLaunchKernelGGL((k3_step<16, 2>), grid, dim3(kThreads), 0, s->st, src, dst, a);
         P3CHK(hipGetLastError());
         src = dst;
         dst = (dst == A) ? B : A;
@@ -588,6 +650,10 @@ pr_status pr3_create(const pr3_problem* p, void* workspace, uint64_t workspace_b
     s->ws = reinterpret_cast<char*>(workspace);
     s->L = L;
     s->st = reinterpret_cast<hipStream_t>(hip_stream);
+    if (const char* e = std::getenv("PR3_TILE_ROWS")) {
+        const int t = std::atoi(e);
+        s->tile_rows = (t == 8 || t == 32) ? t : 16;
+    }
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     s->events = ok;
