@@ -12,7 +12,7 @@
 // kernels.  The truncated DFTs are real GEMMs against cos/sin tables (FP32).
 // The channel contractions (lift, pointwise W, per-mode multipliers,
 // projection, and their gradients) run either in FP32 or in BF16 on MFMA
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation; operands are rounded to bf16
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation; operands are rounded to bf16
 // as they are staged, the master copies stay FP32).  FP64 instances of the
 // same GEMM carry the sine transfers between a fine grid and the FNO grid.
 //
@@ -94,7 +94,7 @@ __device__ inline short to_bf16(float f) {
     return (short)(u >> 16);
 }
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // MF = true: BF16 MFMA (T = float only).  Block tile BM x BN (32x32, 64x32,
@@ -104,8 +104,22 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 //         16x16x16 blocks.
 template <typename T, int BM, int BN, bool MF>
 __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
-    __shared__ T As[KT][BM + 1];
-    __shared__ T Bs[KT][BN + 1];
+    // FMA: FP32 tiles, k-major.  MFMA: bf16 tiles, k fastest (rounded once when
+    // staged), rows padded to 40 elements so that a lane's eight consecutive k
+    // are one aligned 16-byte LDS read.
+    constexpr int KP = KT + 8;
+    __shared__ T As[MF ? 1 : KT][MF ? 1 : BM + 1];
+    __shared__ T Bs[MF ? 1 : KT][MF ? 1 : BN + 1];
+    __shared__ __attribute__((aligned(16))) short Ab[MF ? BM : 1][MF ? KP : 1];
+    __shared__ __attribute__((aligned(16))) short Bb[MF ? BN : 1][MF ? KP : 1];
+    auto put_a = [&](int kk, int mm, T v) __attribute__((always_inline)) {
+        if constexpr (MF) Ab[mm][kk] = to_bf16((float)v);
+        else As[kk][mm] = v;
+    };
+    auto put_b = [&](int kk, int nn, T v) __attribute__((always_inline)) {
+        if constexpr (MF) Bb[nn][kk] = to_bf16((float)v);
+        else Bs[kk][nn] = v;
+    };
     const int tid = threadIdx.x;
     const int bz = blockIdx.z;
     const int i2 = bz % g.n2;
@@ -165,17 +179,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
                         if (k + 2 < g.K) v.z = src[2];
                     }
                 }
-                As[kk][mm] = (T)v.x; As[kk + 1][mm] = (T)v.y;
-                As[kk + 2][mm] = (T)v.z; As[kk + 3][mm] = (T)v.w;
+                put_a(kk, mm, (T)v.x); put_a(kk + 1, mm, (T)v.y);
+                put_a(kk + 2, mm, (T)v.z); put_a(kk + 3, mm, (T)v.w);
             }
         } else {
             for (int e = tid; e < BM * KT; e += kThreads) {
                 int mm, kk;
                 if (a_kfast) { kk = e % KT; mm = e / KT; } else { mm = e % BM; kk = e / BM; }
                 const int m = m0 + mm, k = k0 + kk;
-                As[kk][mm] = (m < g.M && k < g.K)
-                                 ? (m == g.ones_row ? T(1) : A[(long long)m * g.a.rs + (long long)k * g.a.cs])
-                                 : T(0);
+                put_a(kk, mm, (m < g.M && k < g.K)
+                                  ? (m == g.ones_row ? T(1) : A[(long long)m * g.a.rs + (long long)k * g.a.cs])
+                                  : T(0));
             }
         }
         if (b_vec) {
@@ -193,42 +207,36 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs<T> g) {
                         if (n + 2 < g.N) v.z = src[2];
                     }
                 }
-                Bs[kk][nn] = (T)v.x; Bs[kk][nn + 1] = (T)v.y;
-                Bs[kk][nn + 2] = (T)v.z; Bs[kk][nn + 3] = (T)v.w;
+                put_b(kk, nn, (T)v.x); put_b(kk, nn + 1, (T)v.y);
+                put_b(kk, nn + 2, (T)v.z); put_b(kk, nn + 3, (T)v.w);
             }
         } else {
             for (int e = tid; e < KT * BN; e += kThreads) {
                 int kk, nn;
                 if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % KT; nn = e / KT; }
                 const int n = n0 + nn, k = k0 + kk;
-                Bs[kk][nn] = (n < g.N && k < g.K) ? B[(long long)k * g.b.rs + (long long)n * g.b.cs] : T(0);
+                put_b(kk, nn, (n < g.N && k < g.K) ? B[(long long)k * g.b.rs + (long long)n * g.b.cs] : T(0));
             }
         }
         __syncthreads();
         if constexpr (MF) {
+            // one 16x16x32 product per output block and k tile: lane group
+            // lane / 16 holds k = 8 (lane / 16) .. + 7 of its row (A) or column (B)
+            static_assert(KT == 32, "one 16x16x32 MFMA per k tile");
+            const int kb = (lane >> 4) * 8;
+            bf16x8 af[PM], bfr[QN];
 #pragma unroll
-            for (int ks = 0; ks < KT; ks += 16) {
-                const int kb = ks + (lane >> 4) * 4;
-                bf16x4 af[PM], bfr[QN];
+            for (int p = 0; p < PM; ++p)
+                af[p] = *reinterpret_cast<const bf16x8*>(&Ab[wm * 16 * PM + p * 16 + (lane & 15)][kb]);
 #pragma unroll
-                for (int p = 0; p < PM; ++p) {
-                    const int row = wm * 16 * PM + p * 16 + (lane & 15);
+            for (int q = 0; q < QN; ++q)
+                bfr[q] = *reinterpret_cast<const bf16x8*>(&Bb[wn * 16 * QN + q * 16 + (lane & 15)][kb]);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) af[p][e] = to_bf16((float)As[kb + e][row]);
-                }
+            for (int p = 0; p < PM; ++p)
 #pragma unroll
-                for (int q = 0; q < QN; ++q) {
-                    const int col = wn * 16 * QN + q * 16 + (lane & 15);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) bfr[q][e] = to_bf16((float)Bs[kb + e][col]);
-                }
-#pragma unroll
-                for (int p = 0; p < PM; ++p)
-#pragma unroll
-                    for (int q = 0; q < QN; ++q)
-                        macc[p][q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[p], bfr[q],
-                                                                              macc[p][q], 0, 0, 0);
-            }
+                for (int q = 0; q < QN; ++q)
+                    macc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[p], bfr[q], macc[p][q],
+                                                                        0, 0, 0);
         } else {
 #pragma unroll 8
             for (int kk = 0; kk < KT; ++kk) {

@@ -174,6 +174,23 @@ def test_fno_fallback_to_lod(pr):
     net.close()
 
 
+def test_nonfinite_increment_without_fallback(pr):
+    """The same diverging neural G with PR_FLAG_NO_FALLBACK: the norm's
+    non-finite flag ends the solve with PR_ENONFINITE after the first
+    iteration, and the solver stays usable (its serial F is unchanged)."""
+    inst = plain_at_scale(1, M=129, n_slices=8, coarse_M=33)
+    _, flat = gparams(8)
+    say("fno non-finite, no fallback")
+    s, net = make(pr, inst, flat, 1e30, flags=pr.PR_FLAG_NO_FALLBACK)
+    ser0 = s.serial_fine().value.cpu().numpy()
+    with pytest.raises(pr.PararealError) as e:
+        s.solve()
+    assert e.value.status == pr._lib.PR_ENONFINITE
+    assert np.array_equal(s.serial_fine().value.cpu().numpy(), ser0)
+    s.close()
+    net.close()
+
+
 def test_fno_rejected_without_operator(pr):
     inst = plain_at_scale(1, M=129, n_slices=8, coarse_M=33)
     s = pr.Solver(inst, coarse_kind=pr.PR_G_FNO)
