@@ -260,9 +260,16 @@ struct pr_solver {
     std::vector<hipEvent_t> step_ev;   // PR_FLAG_TIME_STEPS: a pair per step launch
     int step_ev_used = 0;
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
+    // Launch shape of the step kernel (measured on the 513^2 x 64 Parareal
+    // solves, where after the chain overlap most sweeps cover 32 slices or
+    // fewer): six fused steps for large sweeps, five for sweeps of at most 32
+    // slices and at most kSmallSweepPoints interior nodes, about 4096
+    // wavefronts per launch in row chunks of at least 24 rows (together +4%
+    // solves/s over 6 / 6144 / 8 everywhere; at 2049^2 x 32 slices, whose row
+    // chunks reach the 128-row cap, six steps stay 9% faster than five).
     int fuse = 6;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
-    int fuse_small = 4;                // ... when a sweep has few slices (PR_STEP_FUSE_SMALL)
-    int small_count = 0;               // "few": at most this many slices (PR_STEP_SMALL_COUNT;
+    int fuse_small = 5;                // ... when a sweep has few slices (PR_STEP_FUSE_SMALL)
+    int small_count = 32;              // "few": at most this many slices (PR_STEP_SMALL_COUNT;
                                        // 0: every sweep uses `fuse`)
     bool weights_ready = false;        // row-weight table of the step kernel written
     bool implicit = false;             // PR_FINE_IMPLICIT
@@ -270,8 +277,8 @@ struct pr_solver {
     int64_t kry_iters = 0;             // BiCGStab iterations of this call (summed over steps)
     int kry_max = 0;                   // most iterations of one step
     int kry_unconv = 0;                // slice-steps that stopped unconverged
-    int wave_target = 6144;            // wavefronts a step launch aims for (PR_STEP_WAVES)
-    int min_rows = 8;                  // shortest row chunk of a step launch (PR_STEP_MINROWS)
+    int wave_target = 4096;            // wavefronts a step launch aims for (PR_STEP_WAVES)
+    int min_rows = 24;                 // shortest row chunk of a step launch (PR_STEP_MINROWS)
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
     std::map<int, double> graph_bytes;
     int ev_every = 8;                  // PR_FLAG_TIME_STEPS: time every ev_every-th launch
@@ -301,6 +308,8 @@ struct pr_solver {
 };
 
 namespace {
+
+constexpr long long kSmallSweepPoints = 32LL * 511 * 511;   // 32 slices of 513^2
 
 #define HIPCHK(expr)                                                                 \
     do {                                                                             \
@@ -417,7 +426,9 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
     // optional: another fused-step count for sweeps over few slices (their
     // launches have few wavefronts; off by default, where it measured within
     // 1% of one count for every sweep)
-    const int fuse = count <= s->small_count ? s->fuse_small : s->fuse;
+    const bool small = count <= s->small_count &&
+                       (long long)count * g.nin * g.nin <= kSmallSweepPoints;
+    const int fuse = small ? s->fuse_small : s->fuse;
     if (s->implicit)
         return implicit_sweep(s, Ubase, first, count, tmp, wres, step_ms, s->dtF, s->mF);
     if (!s->weights_ready) {
