@@ -45,12 +45,12 @@ FP32_VECTOR_NONPACKED_TFLOPS = 78.6
 SEEDS = list(range(8))
 
 
-KERNEL_SOURCES = ("device.hpp", "kernels.hip")
+KERNEL_SOURCES = ("device.hpp", "step_tb.hpp", "kernels.hip")
 
 
 def kernel_source_hash() -> str:
     """First 16 hex digits of sha256 over the step kernel's sources (device.hpp,
-    then kernels.hip)."""
+    step_tb.hpp, then kernels.hip)."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
@@ -893,6 +893,27 @@ def serving_leg(pr, count=120, seed=11, sides=(129, 257)):
                                        "p99_ms": round(r["p99_ms"], 2),
                                        "mean_iters": round(sum(r["iters"]) / count, 2),
                                        "peak_resident": r["peak_resident"]}
+    # the same requests with the fine sweeps of each scheduling pass in shared
+    # (ragged) launches: saturation and the same Poisson arrivals
+    sr = Server(64 << 30, max_resident=64, n_streams=8, ragged=True)
+    r = run_poisson(sr, [0.0] * count, insts)
+    rg = {"saturation": {"solves_per_s": round(r["solves_per_s"], 2),
+                         "p50_ms": round(r["p50_ms"], 2), "p99_ms": round(r["p99_ms"], 2)}}
+    for frac in (0.5, 0.9):
+        t, _ = serving_requests(frac * sat, count, seed=seed, sides=sides)
+        r = run_poisson(sr, t, insts)
+        rg["poisson_%.1fx" % frac] = {"rate": round(frac * sat, 2),
+                                      "solves_per_s": round(r["solves_per_s"], 2),
+                                      "p50_ms": round(r["p50_ms"], 2),
+                                      "p99_ms": round(r["p99_ms"], 2)}
+    st = sr.ragged_stats()
+    rg["shared_launches"] = st["launches"]
+    rg["requests_per_launch"] = round(st["entries"] / max(1, st["launches"]), 2)
+    rg["note"] = ("PR_SERVER_RAGGED_F: the fine sweeps of the requests ready in one scheduling "
+                  "pass share step launches (up to 8 requests each, sweeps bucketed by work "
+                  "per step, a stream per bucket)")
+    out["ragged_fine_launches"] = rg
+    sr.close()
     # the full grid-size mix at saturation only: 1025^2 requests take seconds each
     _, full = serving_requests(1.0, 32, seed=seed + 1, sides=(129, 257, 513, 1025))
     r = run_poisson(sv, [0.0] * len(full), full)

@@ -319,17 +319,29 @@ pr_status parareal_fno_pairs(pr_solver* s, int32_t base, float* pairs_out);
  * iteration or the final write of the result, retires finished requests
  * (their workspace returns to the arena) and admits waiting ones.  Results
  * are bitwise those of parareal_solve on the same request.
+ *
+ * PR_SERVER_RAGGED_F: the fine sweeps (Eq. (parareal)'s F over the active
+ * slices, Sec. 3.1) of every request that a progress pass makes ready for an
+ * iteration run together at the end of that pass, as shared step launches:
+ * sweeps of similar work per step (point-steps per step within a power of 4)
+ * share launches that carry up to eight requests' slices, each with its own
+ * grid, step size and launch geometry (a ragged launch), on one of up to four
+ * extra streams taken in turn.  Each request's coarse chain and correction
+ * follow on its own stream as soon as its own sweep has ended.  Requests
+ * whose Dirichlet data are PR_BC_EXACT keep launches of their own in that
+ * sequence.  Results are unchanged (bitwise).
  * ------------------------------------------------------------------------- */
 typedef struct pr_server pr_server; /* opaque */
 
 typedef struct {
     int32_t max_resident; /* cap on resident requests (>= 1) */
     int32_t n_streams;    /* HIP streams shared by resident requests (1..32) */
-    uint32_t flags;       /* reserved, 0 */
+    uint32_t flags;       /* 0 or PR_SERVER_RAGGED_F */
     int32_t max_queued;   /* waiting (submitted, not yet admitted) requests held at
                              once; 0 = no bound.  Beyond it pr_server_submit
                              refuses the request with PR_EBUSY (load shedding). */
 } pr_server_options;
+#define PR_SERVER_RAGGED_F 1u
 
 typedef struct {
     int32_t status;        /* pr_status of the solve */
@@ -362,6 +374,12 @@ pr_status pr_server_poll(pr_server* sv, int64_t id, int32_t* done, pr_request_in
 pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t* peak_bytes);
 /* Submissions refused with PR_EBUSY since creation. */
 pr_status pr_server_rejected(const pr_server* sv, int64_t* n_rejected);
+/* PR_SERVER_RAGGED_F: progress passes that issued shared fine sweeps, the
+ * shared step launches, and the request entries those launches carried
+ * (entries / launches = requests per launch).  Zeros without the flag; the
+ * pointers may be NULL. */
+pr_status pr_server_ragged_stats(const pr_server* sv, int64_t* ticks, int64_t* launches,
+                                 int64_t* entries);
 /* Blocks until all submitted work has drained, then releases the streams. */
 pr_status pr_server_destroy(pr_server* sv);
 

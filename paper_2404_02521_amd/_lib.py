@@ -27,6 +27,7 @@ PR_FLAG_TIME_STEPS = 1
 PR_FLAG_GRAPH = 2
 PR_FLAG_NO_FALLBACK = 4
 PR_FLAG_SERIAL_CHAIN = 8
+PR_SERVER_RAGGED_F = 1
 PR_FNO_FP32, PR_FNO_BF16 = 0, 1
 PR_FNO_BASE_ZERO, PR_FNO_BASE_IDENTITY, PR_FNO_BASE_LOD, PR_FNO_BASE_FINE_LOD = 0, 1, 2, 3
 PR_FNO_GRID = 64
@@ -143,6 +144,8 @@ SIGNATURES = [
                                  C.POINTER(pr_request_info)]),
     ("pr_server_peaks", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]),
     ("pr_server_rejected", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("pr_server_ragged_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64)]),
     ("pr_server_destroy", C.c_int, [C.c_void_p]),
     ("pr_fno_param_count", C.c_uint64, []),
     ("pr_fno_workspace_bytes", C.c_uint64, [C.c_int32]),

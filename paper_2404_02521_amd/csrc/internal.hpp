@@ -58,6 +58,23 @@ struct StepArgs {
     long long in_off, out_off;   // element offsets of slice `first` in in/out
 };
 
+// One solver's share of a ragged multi-request step launch: its operands, its
+// launch arguments (geometry as for its own launch) and its first workgroup.
+struct TbEntry {
+    const void* in;    // float (increments) or double (states), as the launch's type
+    const float* lb;   // FP32 increment form: dt L b; nullptr for FP64 states
+    void* out;
+    const void* wt;    // the solver's row-weight table
+    StepArgs a;
+    int block0;        // workgroups [block0, next entry's block0) are this entry's
+};
+constexpr int kTbBatchMax = 8;   // entries per launch (about 2 KB of kernel arguments)
+struct TbBatch {
+    int n;         // entries in use
+    int nblocks;   // workgroups of the launch
+    TbEntry e[kTbBatchMax];
+};
+
 // Coarse chain over slices [k0, k1) on a coarse grid of nc nodes per side.
 struct ChainArgs {
     Grid fg;          // fine grid (interior layout)

@@ -30,6 +30,7 @@ hipError_t launch_fine_tb_f32(const float*, const float*, float*, const float*, 
 hipError_t launch_fine_tb_f64(const double*, double*, const double*, const StepArgs&, int,
                               hipStream_t);
 hipError_t launch_row_weights(void*, int, const Coef&, double, int, hipStream_t);
+hipError_t launch_fine_tb_batch(const TbBatch&, bool, int, hipStream_t);
 void tb_geometry(StepArgs&, int, int, int, int);
 int krylov_blocks_per_slice(const Grid&, int);
 hipError_t krylov_step(double*, const KrylovBufs&, const KrylovArgs&, int, int, int*, int*,
@@ -511,6 +512,168 @@ pr_status fine_result_to_state(pr_solver* s, const double* Ubase_slice, const fl
     return PR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Ragged fine sweeps: the F work of several solvers in shared step launches.
+// A solver's sweep is prepared on its own stream (row weights, the FP32
+// preparation step), then the fused-step launches of all solvers run on one
+// stream: per round, each solver takes min(fuse, steps left) steps, and the
+// solvers with the same step count and precision share launches of up to
+// kTbBatchMax entries.  Each entry keeps its solver's launch geometry, so the
+// result is bitwise that of fine_sweep.
+// ---------------------------------------------------------------------------
+struct RaggedSweep {
+    pr_solver* s = nullptr;
+    int first = 0, count = 0;
+    int q = 0;                  // step index of the next launch's input
+    int fuse = 0;               // fused steps per launch
+    long long off = 0;          // element offset of slice `first`
+    const void* cur = nullptr;  // input of the next launch (the FP64 base at q = 0)
+    void* bufA = nullptr;
+    void* bufB = nullptr;
+    const float* Lb = nullptr;  // FP32 increment form: dt L b
+    hipEvent_t done = nullptr;  // recorded on the launch stream after this sweep's last launch
+};
+
+// Prepare the sweep of s over slices [first, first+count) from base Ubase (on
+// s->stream); the step launches follow in ragged_run.
+pr_status ragged_begin(pr_solver* s, const double* Ubase, int first, int count, RaggedSweep* j) {
+    const Grid& g = s->fg;
+    if (s->implicit) return PR_EINVAL;
+    *j = RaggedSweep{};
+    j->s = s;
+    j->first = first;
+    j->count = count;
+    j->off = (long long)first * g.stride;
+    const bool small = count <= s->small_count &&
+                       (long long)count * g.nin * g.nin <= kSmallSweepPoints;
+    j->fuse = small ? s->fuse_small : s->fuse;
+    if (!s->weights_ready) {
+        HIPCHK(launch_row_weights(s->at<char>(s->L.wt), g.n, s->coef, s->dtF, s->fp32 ? 1 : 0,
+                                  s->stream));
+        s->weights_ready = true;
+    }
+    if (s->fp32) {
+        float* A = s->at<float>(s->L.dA) + j->off;
+        float* Lb = s->at<float>(s->L.Lb) + j->off;
+        StepArgs a = step_args(s, g, s->bcf, s->dtF, first, count, 0);
+        HIPCHK(launch_fine_prep(Ubase + j->off, Lb, A, a, s->stream));
+        j->bufA = A;
+        j->bufB = s->at<float>(s->L.dB) + j->off;
+        j->Lb = Lb;
+        j->cur = A;
+        j->q = 1;
+    } else {
+        j->bufA = s->at<double>(s->L.wA) + j->off;
+        j->bufB = s->at<double>(s->L.wB) + j->off;
+        j->cur = Ubase + j->off;
+        j->q = 0;
+    }
+    return PR_OK;
+}
+
+// The step launches of every prepared sweep, on stream st (which must be
+// ordered after each ragged_begin); a sweep's `done` event (when set) is
+// recorded right after its last launch, so that its solver can go on while
+// longer sweeps of the batch still run.  *launches / *entries count the
+// shared launches and the entries they carried.
+pr_status ragged_run(std::vector<RaggedSweep>& jobs, hipStream_t st, int64_t* launches,
+                     int64_t* entries) {
+    std::vector<char> finished(jobs.size(), 0);
+    auto mark_done = [&]() -> pr_status {
+        for (size_t i = 0; i < jobs.size(); ++i) {
+            RaggedSweep& j = jobs[i];
+            if (finished[i] || j.q < j.s->mF) continue;
+            finished[i] = 1;
+            if (j.done && hipEventRecord(j.done, st) != hipSuccess) {
+                j.s->err = "ragged sweep: hipEventRecord failed";
+                return PR_EDEVICE;
+            }
+        }
+        return PR_OK;
+    };
+    for (;;) {
+        const pr_status ms = mark_done();
+        if (ms != PR_OK) return ms;
+        std::map<std::pair<int, int>, std::vector<size_t>> groups;   // (fp32, S) -> jobs
+        for (size_t i = 0; i < jobs.size(); ++i) {
+            RaggedSweep& j = jobs[i];
+            pr_solver* s = j.s;
+            if (j.q >= s->mF) continue;
+            const int S = std::min(j.fuse, s->mF - j.q);
+            void* out = j.cur == j.bufA ? j.bufB : j.bufA;
+            if (s->bcf.kind == PR_BC_EXACT) {
+                // out-of-line closed-form ring: the solver's own launch
+                StepArgs b = tb_args(s, s->fg, s->dtF, j.first, j.count, j.q, S);
+                if (s->fp32)
+                    HIPCHK(launch_fine_tb_f32(static_cast<const float*>(j.cur), j.Lb,
+                                              static_cast<float*>(out), s->at<float>(s->L.wt), b,
+                                              S, st));
+                else
+                    HIPCHK(launch_fine_tb_f64(static_cast<const double*>(j.cur),
+                                              static_cast<double*>(out), s->at<double>(s->L.wt),
+                                              b, S, st));
+                j.cur = out;
+                j.q += S;
+                s->sweep_launches += 1;
+                continue;
+            }
+            groups[{s->fp32 ? 1 : 0, S}].push_back(i);
+        }
+        if (groups.empty()) {
+            bool left = false;
+            for (const RaggedSweep& j : jobs) left = left || j.q < j.s->mF;
+            if (!left) break;
+            continue;   // only own launches this round
+        }
+        for (auto& kv : groups) {
+            const bool fp32 = kv.first.first != 0;
+            const int S = kv.first.second;
+            const std::vector<size_t>& idx = kv.second;
+            for (size_t c = 0; c < idx.size(); c += kTbBatchMax) {
+                TbBatch b{};
+                const size_t ce = std::min(idx.size(), c + (size_t)kTbBatchMax);
+                for (size_t e = c; e < ce; ++e) {
+                    RaggedSweep& j = jobs[idx[e]];
+                    pr_solver* s = j.s;
+                    TbEntry& en = b.e[b.n++];
+                    en.a = tb_args(s, s->fg, s->dtF, j.first, j.count, j.q, S);
+                    en.in = j.cur;
+                    en.out = j.cur == j.bufA ? j.bufB : j.bufA;
+                    en.lb = fp32 ? j.Lb : nullptr;
+                    en.wt = s->at<char>(s->L.wt);
+                    en.block0 = b.nblocks;
+                    b.nblocks += (en.a.count * en.a.nchunks * en.a.nstrips + kBlock / kWave - 1) /
+                                 (kBlock / kWave);
+                }
+                const hipError_t e = launch_fine_tb_batch(b, fp32, S, st);
+                if (e != hipSuccess) {
+                    jobs[idx[c]].s->err = std::string("ragged step launch: ") +
+                                          hipGetErrorString(e);
+                    return PR_EDEVICE;
+                }
+                for (int e2 = 0; e2 < b.n; ++e2) {
+                    RaggedSweep& j = jobs[idx[c + e2]];
+                    j.cur = b.e[e2].out;
+                    j.q += S;
+                    j.s->sweep_launches += 1;
+                }
+                if (launches) *launches += 1;
+                if (entries) *entries += b.n;
+            }
+        }
+    }
+    // the sweeps whose last launch was an own launch of the final round
+    return mark_done();
+}
+
+// The result of a finished ragged sweep, as fine_sweep returns it.
+void ragged_end(const RaggedSweep& j, const float** dres, const double** wres) {
+    if (j.s->fp32)
+        *dres = static_cast<const float*>(j.cur) - j.off;
+    else
+        *wres = static_cast<const double*>(j.cur) - j.off;
+}
+
 ChainArgs chain_args(pr_solver* s, int k0, int k1, int init) {
     ChainArgs a{};
     a.fg = s->fg;
@@ -817,11 +980,13 @@ pr_status iteration_phase_overlapped(pr_solver* s, int k, double* Ucur, double* 
     return PR_OK;
 }
 
+pr_status iteration_after_sweep(pr_solver* s, int k, double* Ucur, double* Unext,
+                                const void* Fold, bool ev);
+
 // Iteration k: F sweep over slices k..N-1, coarse chain, correction + norm
 // into Unext (stream-ordered, no host sync).  step_ms != nullptr enables the
 // per-phase and per-launch timing events.
 pr_status iteration_phase(pr_solver* s, int k, double* Ucur, double* Unext, double* step_ms) {
-    const Grid& g = s->fg;
     const int N = s->N;
     if (s->pipe && !s->fineg && !s->implicit) {
         const int active = N - k;
@@ -834,7 +999,18 @@ pr_status iteration_phase(pr_solver* s, int k, double* Ucur, double* Unext, doub
     const bool ev = step_ms != nullptr && s->events;
     pr_status r = fine_sweep(s, Ucur, k, N - k, false, &d, &w, step_ms);
     if (r != PR_OK) return r;
-    const void* Fold = s->fp32 ? (const void*)d : (const void*)w;
+    return iteration_after_sweep(s, k, Ucur, Unext, s->fp32 ? (const void*)d : (const void*)w,
+                                 ev);
+}
+
+// Iteration k after its fine sweep (Fold: the sweep's result, increments or
+// states): the coarse chain, or the same-grid G slice by slice, and the
+// correction with its norm into Unext.
+pr_status iteration_after_sweep(pr_solver* s, int k, double* Ucur, double* Unext,
+                                const void* Fold, bool ev) {
+    const Grid& g = s->fg;
+    const int N = s->N;
+    pr_status r = PR_OK;
     if (ev) HIPCHK(hipEventRecord(s->ev[1], s->stream));
     unsigned long long* red = s->red();
     HIPCHK(launch_zero_red(red, s->stream));
@@ -1565,9 +1741,20 @@ struct pr_server {
     int max_queued = 0;                   // 0: no bound on waiting requests
     int64_t n_rejected = 0;               // submissions refused with PR_EBUSY
     uint64_t used = 0, peak_bytes = 0;
+    // PR_SERVER_RAGGED_F: the requests that are ready for an iteration gather
+    // here during a progress pass; their fine sweeps then share launches on
+    // one of fstreams (in turn, so that consecutive passes overlap)
+    bool ragged = false;
+    std::vector<hipStream_t> fstreams;
+    std::vector<int64_t> ready;
+    int64_t ragged_ticks = 0, ragged_launches = 0, ragged_entries = 0;
 };
 
 namespace {
+
+// PR_SERVER_RAGGED_F: streams the shared fine launches of successive progress
+// passes take in turn (at most n_streams)
+constexpr int kRaggedStreams = 4;
 
 bool arena_alloc(pr_server* sv, uint64_t bytes, uint64_t* off) {
     bytes = al(bytes);
@@ -1603,17 +1790,85 @@ void arena_free(pr_server* sv, uint64_t off, uint64_t bytes) {
     }
 }
 
-// Enqueue iteration k of request r and the read-back of its norms.
+// The read-back of r's norms after its iteration, and the event progress polls.
+pr_status req_readback(pr_server* sv, Req& r) {
+    pr_solver* s = r.s;
+    HIPCHK(hipMemcpyAsync(sv->pinned + 4 * r.slot, s->red(), 3 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipEventRecord(r.ev, s->stream));
+    return PR_OK;
+}
+
+// Enqueue iteration k of request r and the read-back of its norms (ragged
+// mode: mark r ready; flush_ready enqueues it at the end of the pass).
 pr_status req_enqueue_iteration(pr_server* sv, Req& r) {
+    if (sv->ragged) {
+        sv->ready.push_back(r.id);
+        return PR_OK;
+    }
     pr_solver* s = r.s;
     double* Ucur = s->U(r.k & 1);
     double* Unext = s->U((r.k + 1) & 1);
     pr_status st = iteration_phase(s, r.k, Ucur, Unext, nullptr);
     if (st != PR_OK) return st;
-    HIPCHK(hipMemcpyAsync(sv->pinned + 4 * r.slot, s->red(), 3 * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipEventRecord(r.ev, s->stream));
-    return PR_OK;
+    return req_readback(sv, r);
+}
+
+// The ragged tick: the fine sweeps of every ready request in shared launches,
+// then each request's coarse chain, correction and norm read-back on its own
+// stream, from the end of its own sweep.  Sweeps are bucketed by their work
+// per step (point-steps per step in powers of 4): a bucket shares launches on
+// one of the ragged streams, and different buckets take different streams, so
+// that a small request's rounds do not wait behind a large request's share of
+// the same launch.  On an error every request of the tick is listed in
+// *failed (its work may be partly enqueued).
+pr_status flush_ready(pr_server* sv, std::vector<int64_t>* failed) {
+    const size_t nr = sv->ready.size();
+    std::vector<RaggedSweep> jobs(nr);
+    std::map<int, std::vector<size_t>> buckets;   // log4(points per step) -> jobs
+    pr_status st = PR_OK;
+    for (size_t i = 0; i < nr && st == PR_OK; ++i) {
+        Req& r = sv->reqs[sv->ready[i]];
+        pr_solver* s = r.s;
+        st = ragged_begin(s, s->U(r.k & 1), r.k, s->N - r.k, &jobs[i]);
+        if (st == PR_OK && hipEventRecord(r.ev, s->stream) != hipSuccess) st = PR_EDEVICE;
+        jobs[i].done = r.ev;   // re-recorded on the bucket's stream after the last launch
+        const double pts = (double)(s->N - r.k) * s->fg.nin * s->fg.nin;
+        buckets[(int)std::floor(std::log(std::max(pts, 1.0)) / std::log(4.0))].push_back(i);
+    }
+    int b = 0;
+    for (auto it = buckets.begin(); it != buckets.end() && st == PR_OK; ++it, ++b) {
+        hipStream_t fs = sv->fstreams[(size_t)(sv->ragged_ticks + b) % sv->fstreams.size()];
+        std::vector<RaggedSweep> bj;
+        for (size_t i : it->second) {
+            if (hipStreamWaitEvent(fs, jobs[i].done, 0) != hipSuccess) st = PR_EDEVICE;
+            bj.push_back(jobs[i]);
+        }
+        if (st == PR_OK) st = ragged_run(bj, fs, &sv->ragged_launches, &sv->ragged_entries);
+        for (size_t k = 0; k < it->second.size(); ++k) jobs[it->second[k]] = bj[k];
+    }
+    for (size_t i = 0; i < nr && st == PR_OK; ++i) {
+        Req& r = sv->reqs[sv->ready[i]];
+        pr_solver* s = r.s;
+        if (hipStreamWaitEvent(s->stream, r.ev, 0) != hipSuccess) {
+            st = PR_EDEVICE;
+            break;
+        }
+        const float* d = nullptr;
+        const double* w = nullptr;
+        ragged_end(jobs[i], &d, &w);
+        st = iteration_after_sweep(s, r.k, s->U(r.k & 1), s->U((r.k + 1) & 1),
+                                   s->fp32 ? (const void*)d : (const void*)w, false);
+        if (st == PR_OK) st = req_readback(sv, r);
+    }
+    if (st != PR_OK) {
+        failed->assign(sv->ready.begin(), sv->ready.end());
+        for (hipStream_t fs : sv->fstreams) (void)hipStreamSynchronize(fs);
+    } else {
+        sv->ragged_ticks += 1;
+    }
+    sv->ready.clear();
+    return st;
 }
 
 pr_status req_admit(pr_server* sv, Req& r) {
@@ -1687,7 +1942,8 @@ pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_op
     if (!out || !arena || !opt) return PR_EINVAL;
     *out = nullptr;
     if (reinterpret_cast<uintptr_t>(arena) % kAlign) return PR_EINVAL;
-    if (opt->max_resident < 1 || opt->n_streams < 1 || opt->n_streams > 32 || opt->max_queued < 0)
+    if (opt->max_resident < 1 || opt->n_streams < 1 || opt->n_streams > 32 || opt->max_queued < 0 ||
+        (opt->flags & ~PR_SERVER_RAGGED_F) != 0)
         return PR_EINVAL;
     pr_server* sv = new (std::nothrow) pr_server();
     if (!sv) return PR_ENOMEM;
@@ -1703,6 +1959,18 @@ pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_op
             return PR_EDEVICE;
         }
         sv->streams.push_back(st);
+    }
+    if (opt->flags & PR_SERVER_RAGGED_F) {
+        sv->ragged = true;
+        const int nf = std::min(opt->n_streams, kRaggedStreams);
+        for (int i = 0; i < nf; ++i) {
+            hipStream_t st = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                pr_server_destroy(sv);
+                return PR_EDEVICE;
+            }
+            sv->fstreams.push_back(st);
+        }
     }
     if (hipHostMalloc(reinterpret_cast<void**>(&sv->pinned),
                       sizeof(unsigned long long) * 4 * (size_t)sv->max_resident) != hipSuccess) {
@@ -1799,6 +2067,21 @@ pr_status pr_server_progress(pr_server* sv, int32_t* n_resident, int32_t* n_queu
             sv->resident.pop_back();
         }
     }
+    // 3. ragged mode: the fine sweeps of every request made ready above
+    if (sv->ragged && !sv->ready.empty()) {
+        std::vector<int64_t> failed;
+        const pr_status st = flush_ready(sv, &failed);
+        if (st != PR_OK) {
+            if (first_err == PR_OK) first_err = st;
+            for (int64_t id : failed) {
+                Req& r = sv->reqs[id];
+                r.status = st;
+                if (r.s) (void)hipStreamSynchronize(r.s->stream);
+                req_retire(sv, r);
+                sv->resident.erase(std::find(sv->resident.begin(), sv->resident.end(), id));
+            }
+        }
+    }
     if (n_resident) *n_resident = (int32_t)sv->resident.size();
     if (n_queued) *n_queued = (int32_t)sv->queue.size();
     if (n_done) *n_done = sv->n_done;
@@ -1835,8 +2118,18 @@ pr_status pr_server_rejected(const pr_server* sv, int64_t* n_rejected) {
     return PR_OK;
 }
 
+pr_status pr_server_ragged_stats(const pr_server* sv, int64_t* ticks, int64_t* launches,
+                                 int64_t* entries) {
+    if (!sv) return PR_EINVAL;
+    if (ticks) *ticks = sv->ragged_ticks;
+    if (launches) *launches = sv->ragged_launches;
+    if (entries) *entries = sv->ragged_entries;
+    return PR_OK;
+}
+
 pr_status pr_server_destroy(pr_server* sv) {
     if (!sv) return PR_EINVAL;
+    for (hipStream_t st : sv->fstreams) (void)hipStreamSynchronize(st);
     for (hipStream_t st : sv->streams) (void)hipStreamSynchronize(st);
     for (int64_t id : sv->resident) {
         Req& r = sv->reqs[id];
@@ -1844,6 +2137,7 @@ pr_status pr_server_destroy(pr_server* sv) {
         if (r.s) parareal_destroy(r.s);
     }
     for (hipStream_t st : sv->streams) (void)hipStreamDestroy(st);
+    for (hipStream_t st : sv->fstreams) (void)hipStreamDestroy(st);
     if (sv->pinned) (void)hipHostFree(sv->pinned);
     delete sv;
     return PR_OK;

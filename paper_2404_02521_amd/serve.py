@@ -18,12 +18,15 @@ from .parareal import make_structs
 
 class Server:
     def __init__(self, arena_bytes: int, max_resident: int = 64, n_streams: int = 4,
-                 device=None, max_queued: int = 0):
+                 device=None, max_queued: int = 0, ragged: bool = False):
+        """ragged: PR_SERVER_RAGGED_F (the fine sweeps of the requests ready in a
+        progress pass share step launches)."""
         import torch
         self.device = torch.device(device or "cuda")
         self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
         ptr = (self._arena.data_ptr() + 255) // 256 * 256
-        o = L.pr_server_options(max_resident, n_streams, 0, max_queued)
+        o = L.pr_server_options(max_resident, n_streams,
+                                L.PR_SERVER_RAGGED_F if ragged else 0, max_queued)
         h = C.c_void_p()
         L.check(L.lib().pr_server_create(C.c_void_p(ptr), C.c_uint64(int(arena_bytes)),
                                          C.byref(o), C.byref(h)), "pr_server_create")
@@ -35,11 +38,12 @@ class Server:
         g, _, _, o = make_structs(inst, coarse_kind)
         return int(L.lib().pr_server_footprint(C.byref(g), C.byref(o)))
 
-    def submit(self, inst, coarse_kind: int = L.PR_G_LOD, max_iters: int = 0):
+    def submit(self, inst, coarse_kind: int = L.PR_G_LOD, max_iters: int = 0,
+               bc_kind: int = L.PR_BC_FORWARD_INTRINSIC):
         """Queue a solve; returns its id, or None when the bounded queue refused
         it (PR_EBUSY)."""
         import torch
-        g, m, p, o = make_structs(inst, coarse_kind, max_iters)
+        g, m, p, o = make_structs(inst, coarse_kind, max_iters, bc_kind)
         out = torch.empty((inst.M, inst.M), dtype=torch.float64, device=self.device)
         rid = C.c_int64()
         st = L.lib().pr_server_submit(self._h, C.byref(g), C.byref(m), C.byref(p), C.byref(o),
@@ -54,6 +58,14 @@ class Server:
         n = C.c_int64()
         L.check(L.lib().pr_server_rejected(self._h, C.byref(n)), "pr_server_rejected")
         return n.value
+
+    def ragged_stats(self) -> dict:
+        """Progress passes with shared fine sweeps, shared step launches, and the
+        request entries they carried."""
+        t, n, e = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(L.lib().pr_server_ragged_stats(self._h, C.byref(t), C.byref(n), C.byref(e)),
+                "pr_server_ragged_stats")
+        return {"ticks": t.value, "launches": n.value, "entries": e.value}
 
     def progress(self):
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()

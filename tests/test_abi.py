@@ -42,7 +42,7 @@ def test_constants_match_header(tmp_path):
     names = set(re.findall(r"#define\s+(PR_[A-Z0-9_]+)\s", src))
     names |= set(re.findall(r"\b(PR_[A-Z0-9_]+)\s*=", src))
     names.discard("PR_H")
-    must = {n for n in names if re.match(r"PR_(FLAG|PAYOFF|BC|G|FINE|FP|OP|E|OK|FNO_BASE)", n)}
+    must = {n for n in names if re.match(r"PR_(FLAG|SERVER|PAYOFF|BC|G|FINE|FP|OP|E|OK|FNO_BASE)", n)}
     assert {"PR_FLAG_SERIAL_CHAIN", "PR_G_IMPLICIT", "PR_PAYOFF_CASH_OR_NOTHING"} <= must
     for n in must:
         assert hasattr(L, n), n

@@ -1,13 +1,14 @@
 """Continuous-batching server: each result is the same alone and in the mix
-(bitwise: per-request kernels are deterministic and independent), served
-results match the FP64 oracle's serial F, admission respects the arena and the
-bounded queue, failures are reported per request."""
+(bitwise: per-request kernels are deterministic and independent), also when
+the requests' fine sweeps share ragged launches; served results match the FP64
+oracle's serial F, admission respects the arena and the bounded queue,
+failures are reported per request."""
 import numpy as np
 import pytest
 
 import oracle
 from helpers import oproblem, rel_max, say
-from synthetic import plain_at_scale, serving_requests
+from synthetic import BASKET, EXCHANGE, plain_at_scale, plain_fp64, serving_requests
 
 pytestmark = pytest.mark.gpu
 
@@ -33,12 +34,13 @@ def mix():
     return out
 
 
-def test_alone_vs_mix(pr):
+@pytest.mark.parametrize("ragged", [False, True])
+def test_alone_vs_mix(pr, ragged):
     from paper_2404_02521_amd.serve import Server
     reqs = mix()
     kinds = {"lod": pr.PR_G_LOD, "num": pr.PR_G_NUMERICAL}
-    say("serving mix", len(reqs))
-    sv = Server(2 << 30, max_resident=4, n_streams=3)
+    say("serving mix", len(reqs), "ragged" if ragged else "")
+    sv = Server(2 << 30, max_resident=4, n_streams=3, ragged=ragged)
     ids = [sv.submit(inst, kinds[k]) for inst, k in reqs]
     infos = sv.drain(ids, timeout_s=300)
     for rid, (inst, k) in zip(ids, reqs):
@@ -47,6 +49,34 @@ def test_alone_vs_mix(pr):
         assert infos[rid]["iters"] == alone.iters
         assert np.array_equal(host(sv.result(rid)), host(alone.value)), (inst.M, k)
     assert sv.peaks()[0] <= 4
+    sv.close()
+
+
+def test_ragged_fine_launches(pr):
+    """PR_SERVER_RAGGED_F with every request admitted in the first pass: nine
+    FP32 sweeps of five fused steps (more than one launch's eight entries), an
+    FP64 request and an exact-ring request (its own launches) share the ticks;
+    every result equals its solve alone bitwise, and the shared launches carried
+    more than one request each on average."""
+    from paper_2404_02521_amd.serve import Server
+    B = pr.PR_BC_FORWARD_INTRINSIC
+    reqs = [(inst, pr.PR_G_LOD if k == "lod" else pr.PR_G_NUMERICAL, B) for inst, k in mix()]
+    reqs += [(plain_at_scale(510 + k, M=129, n_slices=32, coarse_M=33).replace(T=0.3),
+              pr.PR_G_LOD, B) for k in range(3)]
+    reqs.append((plain_fp64(BASKET), pr.PR_G_LOD, B))
+    reqs.append((plain_fp64(EXCHANGE), pr.PR_G_NUMERICAL, pr.PR_BC_EXACT))
+    say("ragged launches", len(reqs))
+    sv = Server(4 << 30, max_resident=len(reqs), n_streams=3, ragged=True)
+    ids = [sv.submit(inst, kind, bc_kind=bc) for inst, kind, bc in reqs]
+    infos = sv.drain(ids, timeout_s=300)
+    st = sv.ragged_stats()
+    print("ragged stats", st)
+    assert st["launches"] >= 1 and st["entries"] > st["launches"]
+    for rid, (inst, kind, bc) in zip(ids, reqs):
+        alone = pr.Solver(inst, coarse_kind=kind, bc_kind=bc).solve()
+        assert infos[rid]["status"] in (0, 5)
+        assert infos[rid]["iters"] == alone.iters
+        assert np.array_equal(host(sv.result(rid)), host(alone.value)), (inst.M, kind, bc)
     sv.close()
 
 
@@ -89,7 +119,8 @@ def test_rejects_and_statuses(pr):
     sv.close()
 
 
-def test_served_requests_vs_oracle(pr):
+@pytest.mark.parametrize("ragged", [False, True])
+def test_served_requests_vs_oracle(pr, ragged):
     """Requests of the serving draw (129^2, N in {16, 32, 64}, T ~ U[0.25, 2],
     FP32 F), served in a mix with LOD and numerical coarse propagators: each
     result within 1e-5 relative of the oracle's FP64 serial F (the Parareal
@@ -98,7 +129,7 @@ def test_served_requests_vs_oracle(pr):
     _, insts = serving_requests(1.0, 4, seed=21, sides=(129,))
     kinds = [pr.PR_G_LOD, pr.PR_G_NUMERICAL, pr.PR_G_LOD, pr.PR_G_NUMERICAL]
     say("served vs oracle", [(i.n_slices, round(i.T, 3)) for i in insts])
-    sv = Server(4 << 30, max_resident=4, n_streams=2)
+    sv = Server(4 << 30, max_resident=4, n_streams=2, ragged=ragged)
     ids = [sv.submit(inst, k) for inst, k in zip(insts, kinds)]
     infos = sv.drain(ids, timeout_s=300)
     for rid, inst in zip(ids, insts):
