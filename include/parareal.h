@@ -350,6 +350,9 @@ typedef struct {
     double latency_ms;     /* submit -> result written (host clock) */
     double queue_ms;       /* submit -> admission */
     uint64_t workspace_bytes;
+    int32_t coarse_fallback; /* 1: the neural G diverged and the solve restarted on
+                                the LOD propagator (PR_G_FNO requests) */
+    int32_t reserved_;
 } pr_request_info;
 
 /* Workspace a request needs inside the arena (0 when the arguments are invalid). */
@@ -365,7 +368,10 @@ pr_status pr_server_create(void* arena, uint64_t arena_bytes, const pr_server_op
 pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* model,
                            const pr_payoff* payoff, const pr_options* opt, double* v_out,
                            int64_t* id_out);
-/* One non-blocking scheduling pass.  Counts are written when the pointers are non-NULL. */
+/* One non-blocking scheduling pass.  Counts are written when the pointers are
+ * non-NULL.  Returns the first device or setup error of the pass (the request
+ * concerned is retired with that status); a solve's own outcome (PR_ENOTCONV,
+ * PR_ENONFINITE) is only the request's status in pr_server_poll. */
 pr_status pr_server_progress(pr_server* sv, int32_t* n_resident, int32_t* n_queued,
                              int32_t* n_done);
 /* *done = 1 once the request's result is written; info (may be NULL) is filled then. */
@@ -374,6 +380,17 @@ pr_status pr_server_poll(pr_server* sv, int64_t id, int32_t* done, pr_request_in
 pr_status pr_server_peaks(const pr_server* sv, int32_t* peak_resident, uint64_t* peak_bytes);
 /* Submissions refused with PR_EBUSY since creation. */
 pr_status pr_server_rejected(const pr_server* sv, int64_t* n_rejected);
+/* The neural operator of PR_G_FNO requests (Sec. 3.4; the network, its base
+ * and output scale as created by pr_fno_create): such submissions are refused
+ * with PR_EMODEL while none is attached, and the grid must suit the operator as
+ * for parareal_attach_fno.  Every PR_G_FNO request runs on the server's first
+ * stream, so the operator's activation workspace serves one request at a time;
+ * the caller does not use the handle elsewhere while such requests are queued
+ * or resident, and replacing or clearing it (f = NULL) then gives PR_EINVAL.
+ * A request whose neural G diverges (a non-finite value, or two increments in
+ * a row growing) restarts on the LOD propagator as parareal_solve does, unless
+ * it carries PR_FLAG_NO_FALLBACK (pr_request_info.coarse_fallback). */
+pr_status pr_server_attach_fno(pr_server* sv, pr_fno* f);
 /* PR_SERVER_RAGGED_F: progress passes that issued shared fine sweeps, the
  * shared step launches, and the request entries those launches carried
  * (entries / launches = requests per launch).  Zeros without the flag; the

@@ -90,7 +90,8 @@ class pr_fno_file_info(C.Structure):
 class pr_request_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("last_increment", C.c_double),
                 ("latency_ms", C.c_double), ("queue_ms", C.c_double),
-                ("workspace_bytes", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("coarse_fallback", C.c_int32),
+                ("reserved_", C.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point of include/parareal.h
@@ -146,6 +147,7 @@ SIGNATURES = [
     ("pr_server_rejected", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("pr_server_ragged_stats", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64)]),
+    ("pr_server_attach_fno", C.c_int, [C.c_void_p, C.c_void_p]),
     ("pr_server_destroy", C.c_int, [C.c_void_p]),
     ("pr_fno_param_count", C.c_uint64, []),
     ("pr_fno_workspace_bytes", C.c_uint64, [C.c_int32]),

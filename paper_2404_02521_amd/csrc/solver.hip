@@ -1721,6 +1721,9 @@ struct Req {
     hipEvent_t ev = nullptr;
     pr_status status = PR_OK;
     double inc = 0;
+    double inc_prev[2] = {0.0, 0.0};   // PR_G_FNO: the two increments before the last
+    bool fnog = false;                 // submitted with PR_G_FNO
+    int fallback = 0;                  // the neural G diverged; restarted on LOD
     std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
 };
 
@@ -1740,6 +1743,8 @@ struct pr_server {
     int max_resident = 1, rr = 0, peak_resident = 0, n_done = 0;
     int max_queued = 0;                   // 0: no bound on waiting requests
     int64_t n_rejected = 0;               // submissions refused with PR_EBUSY
+    pr_fno* fno = nullptr;                // operator of PR_G_FNO requests
+    int n_fno = 0;                        // PR_G_FNO requests queued or resident
     uint64_t used = 0, peak_bytes = 0;
     // PR_SERVER_RAGGED_F: the requests that are ready for an iteration gather
     // here during a progress pass; their fine sweeps then share launches on
@@ -1872,7 +1877,9 @@ pr_status flush_ready(pr_server* sv, std::vector<int64_t>* failed) {
 }
 
 pr_status req_admit(pr_server* sv, Req& r) {
-    const int si = sv->rr++ % (int)sv->streams.size();
+    // PR_G_FNO requests share the first stream: one request at a time uses the
+    // operator's activation workspace
+    const int si = r.fnog ? 0 : sv->rr++ % (int)sv->streams.size();
     pr_options o = r.o;
     o.flags &= ~(PR_FLAG_GRAPH | PR_FLAG_TIME_STEPS);
     // requests already overlap across the server's streams: no per-request
@@ -1882,6 +1889,10 @@ pr_status req_admit(pr_server* sv, Req& r) {
                                    sv->streams[si], &r.s);
     if (st != PR_OK) return st;
     pr_solver* s = r.s;
+    if (r.fnog) {
+        st = parareal_attach_fno(s, sv->fno);
+        if (st != PR_OK) return st;
+    }
     if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) return PR_EDEVICE;
     r.slot = sv->free_slots.back();
     sv->free_slots.pop_back();
@@ -1893,6 +1904,7 @@ pr_status req_admit(pr_server* sv, Req& r) {
 }
 
 void req_retire(pr_server* sv, Req& r) {
+    if (r.fnog) sv->n_fno -= 1;
     if (r.ev) (void)hipEventDestroy(r.ev);
     r.ev = nullptr;
     if (r.s) parareal_destroy(r.s);
@@ -1914,6 +1926,21 @@ pr_status req_advance(pr_server* sv, Req& r) {
     std::memcpy(&scint, &h[1], 8);
     r.k += 1;
     r.inc = inc;
+    // PR_G_FNO: a diverging neural G (non-finite, or two increments in a row
+    // growing) restarts the solve on the LOD propagator, as parareal_solve does
+    if (s->fnog && !(s->opt.flags & PR_FLAG_NO_FALLBACK) &&
+        (h[2] || (r.k >= 3 && inc > r.inc_prev[1] && r.inc_prev[1] > r.inc_prev[0]))) {
+        pr_status st = switch_to_lod(s);
+        if (st != PR_OK) return st;
+        r.fallback = 1;
+        r.k = 0;
+        r.inc_prev[0] = r.inc_prev[1] = 0.0;
+        st = init_phase(s, s->U(0), s->U(1));
+        if (st != PR_OK) return st;
+        return req_enqueue_iteration(sv, r);
+    }
+    r.inc_prev[0] = r.inc_prev[1];
+    r.inc_prev[1] = inc;
     const double scale = std::max(scint, s->ring_max_T);
     const double thr = s->opt.tol_relative ? s->opt.tol * scale : s->opt.tol;
     bool stop = false;
@@ -1990,7 +2017,7 @@ pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* m
     int32_t mf = 0, mg = 0;
     pr_status st = parareal_plan(grid, model, opt, &mf, &mg, nullptr, nullptr);
     if (st != PR_OK) return st;
-    if (opt->coarse_kind == PR_G_FNO) return PR_EMODEL;   // requests carry no operator
+    if (opt->coarse_kind == PR_G_FNO && !sv->fno) return PR_EMODEL;   // pr_server_attach_fno
     // the BiCGStab steps poll their convergence on the host; the server never blocks
     if (opt->fine_scheme != PR_FINE_EXPLICIT || opt->coarse_kind == PR_G_IMPLICIT) return PR_EINVAL;
     Req r;
@@ -2008,6 +2035,8 @@ pr_status pr_server_submit(pr_server* sv, const pr_grid* grid, const pr_model* m
         return PR_EBUSY;
     }
     r.t_submit = std::chrono::steady_clock::now();
+    r.fnog = opt->coarse_kind == PR_G_FNO;
+    if (r.fnog) sv->n_fno += 1;
     *id_out = r.id;
     sv->queue.push_back(r.id);
     sv->reqs.emplace(r.id, r);
@@ -2041,7 +2070,10 @@ pr_status pr_server_progress(pr_server* sv, int32_t* n_resident, int32_t* n_queu
             retire = true;   // state 2: the result has been written
         }
         if (retire) {
-            if (r.status != PR_OK && r.status != PR_ENOTCONV && first_err == PR_OK)
+            // a solve's own outcome (not converged, a non-finite iterate) is the
+            // request's status, reported by pr_server_poll only
+            if (r.status != PR_OK && r.status != PR_ENOTCONV && r.status != PR_ENONFINITE &&
+                first_err == PR_OK)
                 first_err = r.status;
             if (r.status != PR_OK && r.s) (void)hipStreamSynchronize(r.s->stream);
             req_retire(sv, r);
@@ -2101,7 +2133,16 @@ pr_status pr_server_poll(pr_server* sv, int64_t id, int32_t* done, pr_request_in
         info->latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
         info->queue_ms = std::chrono::duration<double, std::milli>(r.t_admit - r.t_submit).count();
         info->workspace_bytes = r.bytes;
+        info->coarse_fallback = r.fallback;
+        info->reserved_ = 0;
     }
+    return PR_OK;
+}
+
+pr_status pr_server_attach_fno(pr_server* sv, pr_fno* f) {
+    if (!sv) return PR_EINVAL;
+    if (sv->n_fno > 0 && f != sv->fno) return PR_EINVAL;   // in use by queued or resident requests
+    sv->fno = f;
     return PR_OK;
 }
 

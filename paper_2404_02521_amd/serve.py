@@ -32,18 +32,26 @@ class Server:
                                          C.byref(o), C.byref(h)), "pr_server_create")
         self._h = h
         self._out = {}
+        self._fno = None
 
     @staticmethod
     def footprint(inst, coarse_kind=L.PR_G_LOD) -> int:
         g, _, _, o = make_structs(inst, coarse_kind)
         return int(L.lib().pr_server_footprint(C.byref(g), C.byref(o)))
 
+    def attach_fno(self, fno) -> None:
+        """The operator of PR_G_FNO requests (a paper_2404_02521_amd.fno.Fno, kept
+        alive by the server); None clears it."""
+        L.check(L.lib().pr_server_attach_fno(self._h, fno.handle if fno is not None else None),
+                "pr_server_attach_fno")
+        self._fno = fno
+
     def submit(self, inst, coarse_kind: int = L.PR_G_LOD, max_iters: int = 0,
-               bc_kind: int = L.PR_BC_FORWARD_INTRINSIC):
+               bc_kind: int = L.PR_BC_FORWARD_INTRINSIC, flags: int = 0):
         """Queue a solve; returns its id, or None when the bounded queue refused
         it (PR_EBUSY)."""
         import torch
-        g, m, p, o = make_structs(inst, coarse_kind, max_iters, bc_kind)
+        g, m, p, o = make_structs(inst, coarse_kind, max_iters, bc_kind, flags)
         out = torch.empty((inst.M, inst.M), dtype=torch.float64, device=self.device)
         rid = C.c_int64()
         st = L.lib().pr_server_submit(self._h, C.byref(g), C.byref(m), C.byref(p), C.byref(o),
@@ -82,7 +90,7 @@ class Server:
             return None
         return dict(status=info.status, iters=info.iters, last_increment=info.last_increment,
                     latency_ms=info.latency_ms, queue_ms=info.queue_ms,
-                    workspace_bytes=info.workspace_bytes)
+                    workspace_bytes=info.workspace_bytes, coarse_fallback=info.coarse_fallback)
 
     def result(self, rid: int):
         return self._out[rid]

@@ -178,7 +178,8 @@ def test_fno_host_side_validation():
 
 
 def test_fno_coarse_kind_validation():
-    """PR_G_FNO needs n >= 64; the server refuses it (requests carry no operator)."""
+    """PR_G_FNO needs n >= 64 (the server's refusal without an attached operator
+    is a GPU test: a server owns streams)."""
     inst = plain_at_scale(0, M=33, n_slices=8, coarse_M=9)
     g, m, p, o = make_structs(inst, L.PR_G_FNO)
     assert L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o)) == 0
@@ -186,5 +187,6 @@ def test_fno_coarse_kind_validation():
     g, m, p, o = make_structs(inst, L.PR_G_FNO)
     assert L.lib().parareal_workspace_bytes(C.byref(g), C.byref(o)) > 0
     rid = C.c_int64()
-    assert L.lib().pr_server_submit(C.c_void_p(1), C.byref(g), C.byref(m), C.byref(p), C.byref(o),
-                                    C.c_void_p(1), C.byref(rid)) == L.PR_EMODEL
+    assert L.lib().pr_server_submit(None, C.byref(g), C.byref(m), C.byref(p), C.byref(o),
+                                    C.c_void_p(1), C.byref(rid)) == L.PR_EINVAL
+    assert L.lib().pr_server_attach_fno(None, None) == L.PR_EINVAL

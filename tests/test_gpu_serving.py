@@ -80,6 +80,91 @@ def test_ragged_fine_launches(pr):
     sv.close()
 
 
+def fno_net(seed, scale):
+    """A neural operator with seeded random weights (spectral weights of size
+    1/width, as in the FNO-G parity tests), output scale `scale`."""
+    import torch
+    from oracle import fno as ofno
+    from paper_2404_02521_amd.fno import Fno
+    rng = np.random.default_rng(seed)
+    p = ofno.init_params(rng)
+    for l in range(ofno.N_LAYERS):
+        for k in ("Rr", "Ri"):
+            p[f"{k}{l}"] = rng.normal(0.0, 1.0 / ofno.WIDTH, size=p[f"{k}{l}"].shape)
+    net = Fno(max_batch=1, out_scale=scale, base=1)
+    net.set_params(torch.from_numpy(ofno.flatten(p).astype(np.float32)).cuda())
+    return net
+
+
+@pytest.mark.parametrize("ragged", [False, True])
+def test_fno_requests(pr, ragged):
+    """PR_G_FNO requests through the server with an attached operator, mixed with
+    a LOD request: refused (PR_EMODEL) before the operator is attached, the
+    operator cannot be replaced while they wait, and each result equals the
+    request solved alone with the same operator (status, K, fallback, value
+    bitwise), with the fallback allowed and with PR_FLAG_NO_FALLBACK and tol 0
+    (K = N)."""
+    from paper_2404_02521_amd.serve import Server
+    inst = plain_at_scale(1, M=129, n_slices=8, coarse_M=33)
+    net = fno_net(7, inst.T / inst.n_slices)
+    say("fno requests", "ragged" if ragged else "")
+    sv = Server(2 << 30, max_resident=4, n_streams=3, ragged=ragged)
+    with pytest.raises(pr.PararealError) as e:
+        sv.submit(inst, pr.PR_G_FNO)
+    assert e.value.status == pr._lib.PR_EMODEL
+    sv.attach_fno(net)
+    reqs = [(inst, pr.PR_G_FNO, 0),
+            (inst.replace(tol=0.0), pr.PR_G_FNO, pr.PR_FLAG_NO_FALLBACK),
+            (plain_at_scale(3, M=129, n_slices=8, coarse_M=33), pr.PR_G_LOD, 0),
+            (plain_at_scale(4, M=97, n_slices=8, coarse_M=33), pr.PR_G_FNO, 0)]
+    ids = [sv.submit(i, k, flags=f) for i, k, f in reqs]
+    with pytest.raises(pr.PararealError) as e:
+        sv.attach_fno(None)
+    assert e.value.status == pr._lib.PR_EINVAL
+    infos = sv.drain(ids, timeout_s=300)
+    for rid, (i, k, f) in zip(ids, reqs):
+        s = pr.Solver(i, coarse_kind=k, flags=f)
+        if k == pr.PR_G_FNO:
+            s.attach_fno(net)
+        alone = s.solve()
+        print("K", alone.iters, "fallback", alone.stats["coarse_fallback"])
+        assert infos[rid]["status"] == alone.status
+        assert infos[rid]["iters"] == alone.iters
+        assert infos[rid]["coarse_fallback"] == alone.stats["coarse_fallback"]
+        assert np.array_equal(host(sv.result(rid)), host(alone.value)), (i.M, k, f)
+        s.close()
+    assert infos[ids[1]]["iters"] == inst.n_slices
+    sv.attach_fno(None)   # nothing waits for it any more
+    sv.close()
+    net.close()
+
+
+def test_fno_request_falls_back_to_lod(pr):
+    """A diverging operator (output scale 1e30: the first increment is not
+    finite): the request restarts on LOD G and its result equals a LOD solve
+    with 4 steps per slice, bitwise; with PR_FLAG_NO_FALLBACK it ends with
+    PR_ENONFINITE."""
+    from paper_2404_02521_amd.serve import Server
+    inst = plain_at_scale(1, M=129, n_slices=8, coarse_M=33)
+    net = fno_net(8, 1e30)
+    say("fno request fallback")
+    sv = Server(2 << 30, max_resident=2, n_streams=2)
+    sv.attach_fno(net)
+    ids = [sv.submit(inst, pr.PR_G_FNO), sv.submit(inst, pr.PR_G_FNO,
+                                                   flags=pr.PR_FLAG_NO_FALLBACK)]
+    infos = sv.drain(ids, timeout_s=300)
+    lod = pr.Solver(inst.replace(coarse_steps_per_slice=4), coarse_kind=pr.PR_G_LOD)
+    ref = lod.solve()
+    assert infos[ids[0]]["status"] == 0 and infos[ids[0]]["coarse_fallback"] == 1
+    assert infos[ids[0]]["iters"] == ref.iters
+    assert np.array_equal(host(sv.result(ids[0])), host(ref.value))
+    assert infos[ids[1]]["status"] == pr._lib.PR_ENONFINITE
+    assert infos[ids[1]]["coarse_fallback"] == 0
+    lod.close()
+    sv.close()
+    net.close()
+
+
 def test_admission_by_footprint(pr):
     from paper_2404_02521_amd.serve import Server
     reqs = [plain_at_scale(200 + k, M=129, n_slices=16, coarse_M=33) for k in range(5)]
