@@ -528,8 +528,11 @@ constexpr int kTbPrefetch = 3;
 // 64 - 2S output columns; row chunks sized so that a launch has about
 // wave_target wavefronts, between min_rows and kTbMaxRows rows (rows_override
 // > 0 replaces the rule; every chunk is capped at kTbMaxRows, the rows the
-// kernel's LDS weight table holds).
-void tb_geometry(StepArgs& a, int S, int wave_target, int min_rows, int rows_override) {
+// kernel's LDS weight table holds).  With fit, chunks are then lengthened until
+// the launch has at most wave_target wavefronts: at 4 wavefronts per SIMD the
+// chip holds 4096 of them, and a launch just above that ends with a short
+// second round on a mostly idle chip.
+void tb_geometry(StepArgs& a, int S, int wave_target, int min_rows, int rows_override, int fit) {
     const int W = kWave - 2 * S;
     a.nstrips = (a.g.nin + W - 1) / W;
     long long rows = (long long)a.g.nin * a.nstrips * a.count / wave_target;
@@ -537,6 +540,12 @@ void tb_geometry(StepArgs& a, int S, int wave_target, int min_rows, int rows_ove
     if (rows_override > 0) rows = std::min(rows_override, kTbMaxRows);
     a.rows = (int)std::min<long long>(rows, a.g.nin);
     a.nchunks = (a.g.nin + a.rows - 1) / a.rows;
+    // fit: lengthen the chunks until the launch has at most wave_target wavefronts
+    while (fit && rows_override <= 0 && a.rows < std::min(kTbMaxRows, a.g.nin) &&
+           (long long)a.count * a.nchunks * a.nstrips > wave_target) {
+        a.rows += 1;
+        a.nchunks = (a.g.nin + a.rows - 1) / a.rows;
+    }
 }
 
 template <int MODE, typename T, int S>

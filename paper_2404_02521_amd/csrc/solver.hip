@@ -31,7 +31,7 @@ hipError_t launch_fine_tb_f64(const double*, double*, const double*, const StepA
                               hipStream_t);
 hipError_t launch_row_weights(void*, int, const Coef&, double, int, hipStream_t);
 hipError_t launch_fine_tb_batch(const TbBatch&, bool, int, hipStream_t);
-void tb_geometry(StepArgs&, int, int, int, int);
+void tb_geometry(StepArgs&, int, int, int, int, int);
 int krylov_blocks_per_slice(const Grid&, int);
 hipError_t krylov_step(double*, const KrylovBufs&, const KrylovArgs&, int, int, int*, int*,
                        hipStream_t);
@@ -280,6 +280,7 @@ struct pr_solver {
     int kry_unconv = 0;                // slice-steps that stopped unconverged
     int wave_target = 4096;            // wavefronts a step launch aims for (PR_STEP_WAVES)
     int min_rows = 24;                 // shortest row chunk of a step launch (PR_STEP_MINROWS)
+    int step_fit = 1;                  // PR_STEP_FIT: at most wave_target wavefronts per launch
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
     std::map<int, double> graph_bytes;
     int ev_every = 8;                  // PR_FLAG_TIME_STEPS: time every ev_every-th launch
@@ -297,7 +298,7 @@ struct pr_solver {
     hipEvent_t pipe_ev[kPipeMaxGroups + 1]{};
     int pipe_groups = 2;               // PR_PIPE_GROUPS (1..8; 1 = off)
     int pipe_min = 32;                 // PR_PIPE_MIN: fewest slices per group
-    int pipe_min_rows = 48;            // PR_PIPE_MINROWS: shortest row chunk of a grouped sweep
+    int pipe_min_rows = 24;            // PR_PIPE_MINROWS: shortest row chunk of a grouped sweep
     bool bracket_sweep = true;         // fine_sweep records ev[4] / ev[5] itself
     std::map<int, hipGraphExec_t> graphs;   // key -1: initial sweep, k: iteration k
     std::map<int, hipGraph_t> graph_defs;
@@ -347,7 +348,7 @@ StepArgs step_args(pr_solver* s, const Grid& g, const Bc& bc, double dt, int fir
 // launch has enough wavefronts to fill the chip.
 StepArgs tb_args(pr_solver* s, const Grid& g, double dt, int first, int count, int step, int S) {
     StepArgs a = step_args(s, g, s->bcf, dt, first, count, step);
-    tb_geometry(a, S, s->wave_target, s->min_rows, s->rows_override);
+    tb_geometry(a, S, s->wave_target, s->min_rows, s->rows_override, s->step_fit);
     return a;
 }
 
@@ -1359,6 +1360,7 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     if (const char* e = std::getenv("PR_STEP_WAVES")) s->wave_target = std::max(256, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_TIME_EVERY")) s->ev_every = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("PR_STEP_MINROWS")) s->min_rows = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("PR_STEP_FIT")) s->step_fit = std::atoi(e);
     if (const char* e = std::getenv("PR_PIPE_GROUPS"))
         s->pipe_groups = std::max(1, std::min(pr_solver::kPipeMaxGroups, std::atoi(e)));
     if (const char* e = std::getenv("PR_PIPE_MIN")) s->pipe_min = std::max(1, std::atoi(e));
