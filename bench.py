@@ -923,25 +923,29 @@ def serving_leg(pr, count=120, seed=11, sides=(129, 257)):
                                   "peak_resident": r["peak_resident"],
                                   "peak_arena_gb": round(r["peak_arena_bytes"] / 2 ** 30, 2)}
     sv.close()
-    # the survey's offered loads on the full mix, for one second of arrivals each,
-    # with load shedding: at most 16 requests wait (PR_EBUSY beyond), 16 resident
-    rates = {}
-    for rate in (50.0, 2000.0):
-        t, insts_r = serving_requests(rate, int(rate), seed=seed + 2,
-                                      sides=(129, 257, 513, 1025))
-        sq = Server(64 << 30, max_resident=16, n_streams=8, max_queued=16)
-        r = run_poisson(sq, t, insts_r)
-        row = {"offered_per_s": rate, "arrivals": int(rate), "served": r["served"],
-               "rejected": r["rejected"], "solves_per_s": round(r["solves_per_s"], 3)}
-        if r["served"]:
-            row.update(p50_ms=round(r["p50_ms"], 1), p99_ms=round(r["p99_ms"], 1),
-                       peak_resident=r["peak_resident"])
-        rates["%g_per_s" % rate] = row
-        sq.close()
-        progress("serving at %g req/s done" % rate)
-    out["offered_load_full_mix"] = dict(
-        rates, note="one second of Poisson arrivals per rate; queue bound 16 (refused beyond), "
-                    "16 resident; latency of the served requests, arrival to result")
+    # offered loads of 50 to 2000 requests/s, one second of Poisson arrivals each,
+    # with load shedding (PR_EBUSY beyond the queue bound): on the full mix (16
+    # resident, 16 waiting) and on the {129, 257} sub-mix (64 and 64), where the
+    # rates lie on both sides of saturation
+    for key, sides_r, cap in (("offered_load_full_mix", (129, 257, 513, 1025), 16),
+                              ("offered_load_129_257", sides, 64)):
+        rates = {}
+        for rate in (50.0, 100.0, 200.0, 500.0, 1000.0, 2000.0):
+            t, insts_r = serving_requests(rate, int(rate), seed=seed + 2, sides=sides_r)
+            sq = Server(64 << 30, max_resident=cap, n_streams=8, max_queued=cap)
+            r = run_poisson(sq, t, insts_r)
+            row = {"offered_per_s": rate, "arrivals": int(rate), "served": r["served"],
+                   "rejected": r["rejected"], "solves_per_s": round(r["solves_per_s"], 3)}
+            if r["served"]:
+                row.update(p50_ms=round(r["p50_ms"], 1), p99_ms=round(r["p99_ms"], 1),
+                           peak_resident=r["peak_resident"])
+            rates["%g_per_s" % rate] = row
+            sq.close()
+            progress("serving %s at %g req/s done" % (key, rate))
+        out[key] = dict(rates, note="one second of Poisson arrivals per rate; queue bound %d "
+                                    "(refused beyond), %d resident; latency of the served "
+                                    "requests, arrival to result; solves/s over the served "
+                                    "requests' span" % (cap, cap))
     torch.cuda.empty_cache()
     return out
 
