@@ -117,16 +117,20 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
 #define PR_FLAG_NO_FALLBACK 4u
 /* PR_FLAG_SERIAL_CHAIN: run each iteration's coarse chain and correction after
  * its whole fine sweep, on the solver's stream.  By default (explicit F with the
- * numerical G, no PR_FLAG_GRAPH) an iteration with more than 32 active slices
- * is split into two groups of consecutive slices (the first 32 or half, the
- * rest): the fine sweep runs group by group on the solver's stream, and each
- * group's gather, chain and correction run on a second stream of the solver as
- * soon as its sweep ends, so the chain of one group overlaps the sweep of the
- * next (the chain of a later group restarts from the corrected state at its
- * first slice, which equals the chain's own value there bitwise).  Results are
- * bitwise the same either way.  The phase timings then read: t_fine_ms the
- * fine sweeps, t_chain_ms the chain and correction time left after the last
- * sweep (the exposed part), t_correct_ms 0. */
+ * numerical G, no PR_FLAG_GRAPH) the active slices are split in phases: while
+ * at least 32 slices are active, a phase fixes a boundary B (about two thirds
+ * of the active slices into the first group) and its iterations run two groups
+ * of consecutive slices, [k, B) and [B, N).  The fine sweep runs group by group
+ * on the solver's stream; each group's gather, chain and correction run on a
+ * second stream of the solver as soon as its sweep ends, so the first group's
+ * chain overlaps the second group's sweep; and the next iteration's first-group
+ * sweep, which needs only states the first group's correction has written,
+ * starts beside the second group's chain (it is discarded if the iteration
+ * stops there).  The chain of the second group restarts from the corrected
+ * state at its first slice, which equals the chain's own value there bitwise.
+ * Results are bitwise those of the serial schedule.  In pr_stats, t_fine_ms
+ * covers the fine sweeps, t_chain_ms the chain and correction time left after
+ * the last sweep (the exposed part), t_correct_ms 0. */
 #define PR_FLAG_SERIAL_CHAIN 8u
 
 /* Time stepping of the fine propagator F.  PR_FINE_EXPLICIT: explicit Euler

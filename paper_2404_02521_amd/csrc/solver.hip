@@ -297,7 +297,12 @@ struct pr_solver {
     static constexpr int kPipeMaxGroups = 8;
     hipEvent_t pipe_ev[kPipeMaxGroups + 1]{};
     int pipe_groups = 2;               // PR_PIPE_GROUPS (1..8; 1 = off)
-    int pipe_min = 32;                 // PR_PIPE_MIN: fewest slices per group
+    int pipe_min = 16;                 // PR_PIPE_MIN: fewest slices per group
+    int pipe_mode = 1;                 // PR_PIPE_MODE: 0 equal groups, 1 phases with an early sweep
+    int pipe_split = 67;               // PR_PIPE_SPLIT: percent of a phase's slices in group 0
+    int pipe_B = -1;                   // phased overlap: the current phase's group boundary
+    int early_k = -1;                  // iteration whose first group was swept early
+    const void* early_fold = nullptr;  // that sweep's result (as fine_sweep returns it)
     int pipe_min_rows = 24;            // PR_PIPE_MINROWS: shortest row chunk of a grouped sweep
     bool bracket_sweep = true;         // fine_sweep records ev[4] / ev[5] itself
     std::map<int, hipGraphExec_t> graphs;   // key -1: initial sweep, k: iteration k
@@ -981,6 +986,106 @@ pr_status iteration_phase_overlapped(pr_solver* s, int k, double* Ucur, double* 
     return PR_OK;
 }
 
+// Phased overlap (PR_PIPE_MODE 1).  A phase fixes a group boundary B for the
+// iterations k < B (B - k0 = pipe_split percent of the N - k0 active slices at
+// the phase's first iteration k0; a phase starts while at least 2 pipe_min
+// slices are active, after that an iteration runs as one group): group 0 is
+// [k, B) and shrinks by one slice per iteration, group 1 is [B, N).  As in iteration_phase_overlapped, group 0's chain and
+// correction (chain stream) run beside group 1's fine sweep.  In addition, the
+// next iteration's group-0 sweep [k+1, B) needs only U^{k+1}_{k+1..B}, which
+// group 0's correction has just written, and touches no buffer that group 1
+// still reads (its slices are below B): it is issued right after that
+// correction and runs beside group 1's chain, the part of the chain that the
+// equal-group schedule leaves exposed.  If the solve stops at k, that sweep is
+// discarded.  The arithmetic of every slice is unchanged.
+pr_status iteration_phase_phased(pr_solver* s, int k, double* Ucur, double* Unext,
+                                 double* step_ms) {
+    const Grid& g = s->fg;
+    const int N = s->N;
+    const int B = s->pipe_B;
+    const bool ev = step_ms != nullptr && s->events;
+    hipStream_t cs = s->chain_stream;
+    unsigned long long* red = s->red();
+    HIPCHK(launch_zero_red(red, s->stream));
+    if (k > 0)
+        HIPCHK(hipMemcpyAsync(Unext + (long long)k * g.stride, Ucur + (long long)k * g.stride,
+                              (size_t)g.stride * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (ev) HIPCHK(hipEventRecord(s->ev[4], s->stream));
+    struct Restore {   // the sweep settings come back on every return
+        pr_solver* s;
+        int min_rows;
+        ~Restore() {
+            s->min_rows = min_rows;
+            s->bracket_sweep = true;
+        }
+    } restore{s, s->min_rows};
+    s->min_rows = std::max(restore.min_rows, s->pipe_min_rows);
+    s->bracket_sweep = false;
+    auto fold = [&](const float* d, const double* w) {
+        return s->fp32 ? (const void*)d : (const void*)w;
+    };
+    // group 0: [k, B), swept during the previous iteration when it could be
+    const void* F0 = nullptr;
+    if (s->early_k == k) {
+        F0 = s->early_fold;
+    } else {
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, Ucur, k, B - k, false, &d, &w, step_ms);
+        if (r != PR_OK) return r;
+        F0 = fold(d, w);
+    }
+    s->early_k = -1;
+    HIPCHK(hipEventRecord(s->pipe_ev[0], s->stream));
+    HIPCHK(hipStreamWaitEvent(cs, s->pipe_ev[0], 0));
+    HIPCHK(launch_gather_coincident(Ucur, F0, s->at<double>(s->L.foldc), g, s->nc, s->q, k, B,
+                                    s->fp32 ? 1 : 0, cs));
+    ChainArgs c0 = chain_args(s, k, B, 0);
+    HIPCHK(launch_chain(Ucur, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+                        s->at<double>(s->L.cst), s->at<float>(s->L.lbc), c0, cs));
+    HIPCHK(launch_correct(Ucur, F0, s->at<double>(s->L.dcor), nullptr, nullptr, Unext, red, g, k,
+                          B, N, s->nc, s->q, s->fp32, 0, cs));
+    HIPCHK(hipEventRecord(s->pipe_ev[2], cs));   // U^{k+1}_{k+1..B} written
+    // group 1: [B, N)
+    {
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, Ucur, B, N - B, false, &d, &w, step_ms);
+        if (r != PR_OK) return r;
+        const void* F1 = fold(d, w);
+        HIPCHK(hipEventRecord(s->pipe_ev[1], s->stream));
+        HIPCHK(hipStreamWaitEvent(cs, s->pipe_ev[1], 0));
+        HIPCHK(launch_gather_coincident(Ucur, F1, s->at<double>(s->L.foldc), g, s->nc, s->q, B,
+                                        N, s->fp32 ? 1 : 0, cs));
+        ChainArgs c1 = chain_args(s, B, N, 0);
+        HIPCHK(launch_chain(Unext, s->at<double>(s->L.Gold), s->at<double>(s->L.dcor),
+                            s->at<double>(s->L.cst), s->at<float>(s->L.lbc), c1, cs));
+        HIPCHK(launch_correct(Ucur, F1, s->at<double>(s->L.dcor), nullptr, nullptr, Unext, red,
+                              g, B, N, N, s->nc, s->q, s->fp32, 0, cs));
+    }
+    // the next iteration's group 0, beside group 1's chain
+    if (k + 1 < B && k + 1 < s->maxit) {
+        HIPCHK(hipStreamWaitEvent(s->stream, s->pipe_ev[2], 0));
+        const float* d = nullptr;
+        const double* w = nullptr;
+        pr_status r = fine_sweep(s, Unext, k + 1, B - k - 1, false, &d, &w, step_ms);
+        if (r != PR_OK) return r;
+        s->early_fold = fold(d, w);
+        s->early_k = k + 1;
+    }
+    if (ev) {
+        HIPCHK(hipEventRecord(s->ev[5], s->stream));
+        HIPCHK(hipEventRecord(s->ev[1], s->stream));
+    }
+    HIPCHK(hipEventRecord(s->pipe_ev[3], cs));
+    HIPCHK(hipStreamWaitEvent(s->stream, s->pipe_ev[3], 0));
+    if (ev) {
+        HIPCHK(hipEventRecord(s->ev[2], s->stream));
+        HIPCHK(hipEventRecord(s->ev[3], s->stream));
+    }
+    return PR_OK;
+}
+
 pr_status iteration_after_sweep(pr_solver* s, int k, double* Ucur, double* Unext,
                                 const void* Fold, bool ev);
 
@@ -989,7 +1094,14 @@ pr_status iteration_after_sweep(pr_solver* s, int k, double* Ucur, double* Unext
 // per-phase and per-launch timing events.
 pr_status iteration_phase(pr_solver* s, int k, double* Ucur, double* Unext, double* step_ms) {
     const int N = s->N;
-    if (s->pipe && !s->fineg && !s->implicit) {
+    if (s->pipe && !s->fineg && !s->implicit && s->pipe_mode == 1) {
+        if (k >= s->pipe_B) {   // a new phase: split the active slices in two
+            const int active = N - k;
+            const int g0 = std::max(1, std::min(active - 1, active * s->pipe_split / 100));
+            s->pipe_B = active >= 2 * s->pipe_min ? k + g0 : N;
+        }
+        if (s->pipe_B > k && s->pipe_B < N) return iteration_phase_phased(s, k, Ucur, Unext, step_ms);
+    } else if (s->pipe && !s->fineg && !s->implicit) {
         const int active = N - k;
         const int gs = std::max(s->pipe_min, (active + s->pipe_groups - 1) / s->pipe_groups);
         const int G = (active + gs - 1) / gs;
@@ -1111,6 +1223,8 @@ pr_status do_solve(pr_solver* s, double* v_out, pr_stats* st) {
     }
     bool diverging = false;   // PR_G_FNO: non-finite, or two increments in a row growing
     reset_krylov_stats(s);
+    s->pipe_B = -1;   // the phased overlap starts a new phase at k = 0
+    s->early_k = -1;
     s->timed_launches = 0;
     s->timed_bytes = 0;
     double* Ucur = s->U(0);
@@ -1364,6 +1478,9 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     if (const char* e = std::getenv("PR_PIPE_GROUPS"))
         s->pipe_groups = std::max(1, std::min(pr_solver::kPipeMaxGroups, std::atoi(e)));
     if (const char* e = std::getenv("PR_PIPE_MIN")) s->pipe_min = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("PR_PIPE_MODE")) s->pipe_mode = std::atoi(e);
+    if (const char* e = std::getenv("PR_PIPE_SPLIT"))
+        s->pipe_split = std::max(1, std::min(99, std::atoi(e)));
     if (const char* e = std::getenv("PR_PIPE_MINROWS")) s->pipe_min_rows = std::max(1, std::atoi(e));
     if (!s->fineg && chain_set_lds(chain_lds_bytes(s->nc, s->fp32 ? 1 : 0)) != hipSuccess)
         return PR_EDEVICE;
@@ -1389,7 +1506,7 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
     if (!s->graph && !(opt->flags & PR_FLAG_SERIAL_CHAIN) && !s->implicit && s->pipe_groups > 1 &&
         hipStreamCreateWithFlags(&s->chain_stream, hipStreamNonBlocking) == hipSuccess) {
         bool eok = true;
-        for (int i = 0; i <= s->pipe_groups; ++i)
+        for (int i = 0; i <= std::max(s->pipe_groups, 3); ++i)
             eok = eok && hipEventCreateWithFlags(&s->pipe_ev[i], hipEventDisableTiming) == hipSuccess;
         s->pipe = eok;   // otherwise the chain stays serial (the objects are released later)
     }

@@ -1,12 +1,16 @@
 """The overlapped coarse chain (default for explicit F with the numerical G):
 the fine sweep runs slice group by slice group while a second stream runs each
 finished group's chain and correction, Eq. (parareal) (Sec. 3.1) unchanged.
+Two schedules: equal groups (PR_PIPE_MODE 0), and phases with a fixed group
+boundary whose next first-group sweep starts beside the current second-group
+chain (PR_PIPE_MODE 1, the default).
 
 Checks: bitwise equality with the serial schedule (PR_FLAG_SERIAL_CHAIN) at the
-at-scale shape (513^2 FP32, N = 64, chain on 129^2; two groups while more than
-32 slices are active) after a few iterations and to convergence; with smaller
-and more groups forced (PR_PIPE_MIN, PR_PIPE_GROUPS), the same equality and
-parity with the oracle's Parareal in FP64.
+at-scale shape (513^2 FP32, N = 64, chain on 129^2) after a few iterations and
+to convergence; with smaller groups forced (PR_PIPE_MIN, PR_PIPE_GROUPS) in
+both schedules, the same equality, parity with the oracle's Parareal in FP64
+and finite termination; a tolerance stop inside a phase (the early sweep is
+discarded) followed by a second solve on the same solver.
 """
 import numpy as np
 import pytest
@@ -55,13 +59,16 @@ def test_overlap_bitwise_at_scale(pr, seed, k):
           "| serial: fine ms", sb["t_fine_ms"], "chain ms", sb["t_chain_ms"])
 
 
+@pytest.mark.parametrize("mode", ["0", "1"])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_overlap_small_groups_vs_oracle(pr, monkeypatch, k):
-    """65^2 FP64, N = 8 in groups of 2 (4 groups, each later group's chain
-    restarting from the corrected state): against the oracle's Parareal and
-    bitwise against the serial schedule."""
+def test_overlap_small_groups_vs_oracle(pr, monkeypatch, k, mode):
+    """65^2 FP64, N = 8: equal groups of 2 (mode 0: 4 groups, each later
+    group's chain restarting from the corrected state) or phases of two groups
+    down to 2 slices (mode 1): against the oracle's Parareal and bitwise
+    against the serial schedule."""
     monkeypatch.setenv("PR_PIPE_MIN", "2")
     monkeypatch.setenv("PR_PIPE_GROUPS", "4")
+    monkeypatch.setenv("PR_PIPE_MODE", mode)
     inst = plain_fp64(BASKET).replace(tol=0.0)
     say("overlap small groups", k)
     (a, ia, ka, _), (b, ib, _, _) = both(pr, inst, max_iters=k)
@@ -73,12 +80,15 @@ def test_overlap_small_groups_vs_oracle(pr, monkeypatch, k):
     assert np.array_equal(a, b) and ia == ib
 
 
-def test_overlap_small_groups_finite_termination(pr, monkeypatch):
-    """129^2 FP32 over 33^2, N = 16 in three groups (6, 6, 4 slices while 16 are
-    active; ragged groups as the active count shrinks): K = N equals serial F
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_overlap_small_groups_finite_termination(pr, monkeypatch, mode):
+    """129^2 FP32 over 33^2, N = 16: three equal groups (mode 0: 6, 6, 4 slices
+    while 16 are active; ragged groups as the active count shrinks) or phases
+    with boundaries at slices 8, 12 and 14 (mode 1): K = N equals serial F
     bitwise."""
     monkeypatch.setenv("PR_PIPE_MIN", "3")
     monkeypatch.setenv("PR_PIPE_GROUPS", "3")
+    monkeypatch.setenv("PR_PIPE_MODE", mode)
     inst = plain_at_scale(5, M=129, n_slices=16, coarse_M=33).replace(tol=0.0)
     say("overlap finite termination")
     s = pr.Solver(inst)
@@ -86,4 +96,31 @@ def test_overlap_small_groups_finite_termination(pr, monkeypatch):
     ser = host(s.serial_fine().value)
     assert r.iters == 16
     assert np.array_equal(host(r.value), ser)
+    s.close()
+
+
+def test_phased_stop_inside_a_phase(pr, monkeypatch):
+    """Phases down to 2 slices, 129^2 FP32 over 33^2, N = 16 (first phase: the
+    boundary at slice 8), with an absolute tolerance between the 4th and 5th
+    increments of the run to K = N: the solve stops inside the first phase,
+    with the next iteration's first-group sweep already issued and discarded.
+    Equal to the serial schedule bitwise, and a second solve on the same solver
+    repeats the first."""
+    monkeypatch.setenv("PR_PIPE_MIN", "2")
+    monkeypatch.setenv("PR_PIPE_MODE", "1")
+    base = plain_at_scale(6, M=129, n_slices=16, coarse_M=33).replace(tol=0.0,
+                                                                     tol_relative=False)
+    s = pr.Solver(base, flags=pr.PR_FLAG_SERIAL_CHAIN)
+    inc = list(s.solve().increments)
+    s.close()
+    inst = base.replace(tol=0.5 * (inc[3] + inc[4]))
+    say("phased stop inside a phase", inc[:6])
+    (a, ia, ka, _), (b, ib, kb, _) = both(pr, inst)
+    print("iters", ka)
+    assert ka == kb and 2 <= ka < 8
+    assert ia == ib and np.array_equal(a, b)
+    s = pr.Solver(inst)
+    r1, r2 = s.solve(), s.solve()
+    assert r1.iters == r2.iters == ka
+    assert np.array_equal(host(r1.value), a) and np.array_equal(host(r2.value), a)
     s.close()
