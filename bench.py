@@ -293,8 +293,8 @@ def main():
     # point-steps of the event-timed step launches (12 B algorithmic per point-step)
     pts_per_s = steps_bytes / 12.0 / (steps_ms * 1e-3) if steps_ms > 0 else 0.0
     achieved_tflops = pts_per_s * FLOPS_PER_POINT_STEP / 1e12
-    # the dominant launch of these solves: a sweep of 32 slices or fewer (the
-    # overlapped chain's groups and every late iteration), five fused steps
+    # the profile of these solves' launches: a sweep of 32 slices at 513^2 (the
+    # phased overlap's groups and the late iterations cover 1 to 42 slices)
     head = profile_figures("k_fine_tb_513x513x32_fp32.md")
     share = profile_figures("k_fine_tb_2049x2049x32_fp32.md")
     avg_launch_us = steps_ms * 1e3 / max(1, steps_launch)
@@ -335,7 +335,7 @@ def main():
             "bound": "alu", "achieved": round(achieved_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
             "traffic": traffic,
-            "kernel": "k_fine_tb<MODE_INCR, S=5 for sweeps of <= 32 slices, 6 above> (FP32 "
+            "kernel": "k_fine_tb<MODE_INCR, S=5 for sweeps of <= 16 slices, 6 above> (FP32 "
                       "increment form, S explicit steps per launch "
                       "in registers, neighbour weights with dt folded in)",
             "why_alu": "rocprofv3 SQ counters: the kernel issues VALU instructions at the chip's "

@@ -262,15 +262,14 @@ struct pr_solver {
     int step_ev_used = 0;
     int rows_override = 0;             // PR_STEP_ROWS (tuning): rows per wavefront chunk
     // Launch shape of the step kernel (measured on the 513^2 x 64 Parareal
-    // solves, where after the chain overlap most sweeps cover 32 slices or
-    // fewer): six fused steps for large sweeps, five for sweeps of at most 32
-    // slices and at most kSmallSweepPoints interior nodes, about 4096
-    // wavefronts per launch in row chunks of at least 24 rows (together +4%
-    // solves/s over 6 / 6144 / 8 everywhere; at 2049^2 x 32 slices, whose row
-    // chunks reach the 128-row cap, six steps stay 9% faster than five).
+    // solves with the phased chain overlap, whose sweeps cover 1 to 42
+    // slices): six fused steps, five for sweeps of at most 16 slices and at
+    // most kSmallSweepPoints interior nodes, at most 4096 wavefronts per
+    // launch in row chunks of at least 24 rows (at 2049^2 x 32 slices, whose
+    // row chunks reach the 128-row cap, six steps stay 9% faster than five).
     int fuse = 6;                      // explicit steps per launch (PR_STEP_FUSE, 1..8)
     int fuse_small = 5;                // ... when a sweep has few slices (PR_STEP_FUSE_SMALL)
-    int small_count = 32;              // "few": at most this many slices (PR_STEP_SMALL_COUNT;
+    int small_count = 16;              // "few": at most this many slices (PR_STEP_SMALL_COUNT;
                                        // 0: every sweep uses `fuse`)
     bool weights_ready = false;        // row-weight table of the step kernel written
     bool implicit = false;             // PR_FINE_IMPLICIT
