@@ -32,6 +32,8 @@
 #include <new>
 #include <string>
 
+#include "device.hpp"
+
 #include "parareal3.h"
 
 namespace pr3 {
@@ -71,6 +73,9 @@ struct Step3 {
     int first;           // absolute index of the launch's slice 0
     int rows;            // i-planes per workgroup
     int ntk;             // k tiles
+    int ntiles;          // (j, k) tiles per plane chunk
+    int nchunks;         // plane chunks per slice
+    int xcd;             // 1: XCD-aware workgroup order
 };
 
 // TJ j-rows per tile, RJ rows per thread (rows tj, tj + TJ / RJ, ...).
@@ -87,13 +92,18 @@ __global__ __launch_bounds__(kThreads) void k3_step(const double* __restrict__ i
     __shared__ double pl[kSlots][kTJ + 2][kTK + 2];
     const G3& g = a.g;
     const int tk = threadIdx.x % kTK, tj = threadIdx.x / kTK;
-    const int kt = blockIdx.x % a.ntk, jt = blockIdx.x / a.ntk;
+    // one-dimensional grid, renumbered so that each XCD takes a contiguous run
+    // of (tile, plane chunk, slice): neighbouring tiles and chunks then share
+    // that XCD's L2, where their halo planes and rows are read again
+    const int bid = a.xcd ? pr::xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = bid % a.ntiles, chunk = (bid / a.ntiles) % a.nchunks;
+    const int kt = tile % a.ntk, jt = tile / a.ntk;
     const int jb = jt * kTJ, kb = kt * kTK;   // node indices of the tile's halo row / column
-    const int s = blockIdx.z;
+    const int s = bid / (a.ntiles * a.nchunks);
     const long long base = (long long)s * g.stride;
     const double tau = (a.first + s) * a.dT + a.tq;
     const double disc = exp(-a.b.r * tau);
-    const int i0 = 1 + blockIdx.y * a.rows, i1 = min(i0 + a.rows - 1, g.nin);
+    const int i0 = 1 + chunk * a.rows, i1 = min(i0 + a.rows - 1, g.nin);
     // the halo elements this thread loads, mapped once: node (j, k), whether it
     // lies on the grid and whether it is interior in j and k
     int ej[kPer], ek[kPer];
@@ -400,6 +410,7 @@ struct pr3_solver {
     hipEvent_t ev[4]{};
     bool events = false;
     int tile_rows = 16;   // j-rows per step tile: 8, 16 or 32 (PR3_TILE_ROWS)
+    int xcd = 1;          // XCD-aware workgroup order of the step kernel (PR3_XCD; 0: off)
     std::string err;
     template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
 };
@@ -438,7 +449,10 @@ pr_status sweep(pr3_solver* s, const G3& g, const C3& c, const B3& b, const doub
     const int TJ = s->tile_rows;
     const int ntj = (g.nin + TJ - 1) / TJ;
     a.rows = step_rows(g, a.ntk * ntj, count);
-    const dim3 grid(a.ntk * ntj, (g.nin + a.rows - 1) / a.rows, count);
+    a.ntiles = a.ntk * ntj;
+    a.nchunks = (g.nin + a.rows - 1) / a.rows;
+    a.xcd = s->xcd;
+    const dim3 grid(a.ntiles * a.nchunks * count);
     const double* src = in;
     double* dst = A;
     for (int q = 0; q < m; ++q) {
@@ -654,6 +668,7 @@ pr_status pr3_create(const pr3_problem* p, void* workspace, uint64_t workspace_b
         const int t = std::atoi(e);
         s->tile_rows = (t == 8 || t == 32) ? t : 16;
     }
+    if (const char* e = std::getenv("PR3_XCD")) s->xcd = std::atoi(e) != 0;
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     s->events = ok;
