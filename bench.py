@@ -297,6 +297,9 @@ def main():
     # phased overlap's groups and the late iterations cover 1 to 42 slices)
     head = profile_figures("k_fine_tb_513x513x32_fp32.md")
     share = profile_figures("k_fine_tb_2049x2049x32_fp32.md")
+    # the kernel trace of this command (bench.py itself): the step kernel's
+    # average duration without the events' dispatch delay
+    trace = profile_figures("k_fine_tb_headline_513x513x64_fp32.md")
     avg_launch_us = steps_ms * 1e3 / max(1, steps_launch)
     pts_per_launch = steps_bytes / 12.0 / max(1, steps_launch)
     traffic = (round(head["hbm_bytes_per_point_step"] * pts_per_launch)
@@ -356,6 +359,10 @@ def main():
                 "valu_instr_per_point_step", "valu_issue_frac", "achieved_tflops")},
             "kernel_source_sha256": kernel_source_hash(),
             "avg_launch_us": round(avg_launch_us, 3),
+            "kernel_trace_avg_launch_us": trace.get("kernel_trace_avg_launch_us"),
+            "achieved_with_kernel_trace_duration": (
+                round(achieved_tflops * avg_launch_us / trace["kernel_trace_avg_launch_us"], 3)
+                if trace.get("kernel_trace_avg_launch_us") else None),
             "point_steps_per_launch": round(pts_per_launch),
             "timed_launches": steps_launch, "all_launches": all_launch},
     }
