@@ -38,33 +38,32 @@ namespace pr {
 constexpr int kKBlock = 256;
 constexpr int kMaxRestarts = 4;
 
-// Sum of `n` partial values (stride `st`) in a fixed order, broadcast to the
-// whole workgroup: thread t adds t, t + 256, ...; then a fixed tree.
-__device__ double block_sum_fixed(const double* part, int n, int st, double* sm) {
-    double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += kKBlock) v += part[(long long)k * st];
-    sm[threadIdx.x] = v;
+static_assert(kKBlock == 4 * 64, "the workgroup sums below combine four wavefronts");
+
+// Sum of a per-lane value over the wavefront in a fixed pairing (lane l takes
+// lane l + o for o = 32, 16, ..., 1): the total is in lane 0.
+__device__ inline double wave_sum_fixed(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Workgroup sum of a per-thread value in a fixed order (each wavefront, then
+// the four wavefront sums), the same bits in every thread.
+__device__ double block_sum_tree(double v, double* sm) {
+    v = wave_sum_fixed(v);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int o = kKBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double r = sm[0];
-    __syncthreads();
+    const double r = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+    __syncthreads();   // sm is reused by the next sum
     return r;
 }
 
-// Workgroup sum of a per-thread value (fixed tree), result in thread 0.
-__device__ double block_sum_tree(double v, double* sm) {
-    sm[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = kKBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double r = sm[0];
-    __syncthreads();
-    return r;
+// Sum of `n` partial values (stride `st`) in a fixed order, broadcast to the
+// whole workgroup: thread t adds t, t + 256, ...; then block_sum_tree.
+__device__ double block_sum_fixed(const double* part, int n, int st, double* sm) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += kKBlock) v += part[(long long)k * st];
+    return block_sum_tree(v, sm);
 }
 
 // Row (i, j) of (I - dt L_h) in index form.
