@@ -109,3 +109,28 @@ def test_lod_max_size_2049(pr):
     ref = oracle.lod(p, 1, inst.T, 0.0, u0)
     assert abs_max(got, ref) <= 1e-12
     s.close()
+
+
+def test_lod_solvers_of_several_sizes(pr):
+    """Solvers of several grid sizes in one process: the 2049^2 line solver
+    (the largest LDS footprint) and the 513^2 two-column x stage still give
+    their first results bitwise after smaller LOD solvers have been created
+    (each creation sets the kernels' shared-memory limit)."""
+    from synthetic import largest_single
+    big = largest_single().replace(n_slices=1, T=1e-3, fine_steps_per_slice=0,
+                                   coarse_steps_per_slice=1, fp32=False)
+    mid = plain_at_scale(3, M=513, n_slices=2, coarse_M=129).replace(T=0.01, fp32=False)
+    say("lod solvers of several sizes")
+    sb = pr.Solver(big, coarse_kind=pr.PR_G_LOD)
+    sm = pr.Solver(mid, coarse_kind=pr.PR_G_LOD)
+    ub, um = to_dev(oracle.payoff_grid(oproblem(big))), to_dev(oracle.payoff_grid(oproblem(mid)))
+    gb0 = host(sb.apply(pr.PR_OP_COARSE, 0, ub))
+    gm0 = host(sm.apply(pr.PR_OP_COARSE, 0, um))
+    small = [pr.Solver(plain_fp64(BASKET).replace(M=M, fine_steps_per_slice=0,
+                                                  coarse_steps_per_slice=0),
+                       coarse_kind=pr.PR_G_LOD)
+             for M in (33, 65, 129)]
+    assert np.array_equal(host(sb.apply(pr.PR_OP_COARSE, 0, ub)), gb0)
+    assert np.array_equal(host(sm.apply(pr.PR_OP_COARSE, 0, um)), gm0)
+    for s in small + [sb, sm]:
+        s.close()
