@@ -126,6 +126,9 @@ struct KrylovBufs {
     double *partA, *partB, *partC;           // count * nblk (* 2) partial sums
     KScal* sc;                               // count scalar records
     int* ndone;                              // finished-slice counter (device)
+    int* hpoll;                              // 2 pinned host slots for ndone, or nullptr:
+    void* pev[2];                            // with their events (hipEvent_t), the host
+                                             // reads a poll one round of iterations late
 };
 
 }  // namespace pr

@@ -459,7 +459,14 @@ hipError_t krylov_step(double* X, const KrylovBufs& b, const KrylovArgs& a0, int
     hipLaunchKernelGGL(k_kry_start, dim3(a.count), blk, 0, st, b.partC, b.sc, b.ndone, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int it = 0, nd = 0;
+    // Pipelined polls (b.hpoll set): the finished-slice count is copied to a
+    // pinned slot every poll_every iterations and read one round later, while
+    // the next round is already queued, so the device never waits for the
+    // host.  The iterations queued after the round that finished every slice
+    // return at once (finished slices skip their work); they are not counted.
+    const bool piped = b.hpoll != nullptr && b.pev[0] != nullptr && b.pev[1] != nullptr;
+    int it = 0, nd = 0, idle = 0;
+    int pending = -1, pending_it = 0, polls = 0;
     for (;;) {
         for (; it < max_iters; ++it) {
             a.it = it;
@@ -471,14 +478,35 @@ hipError_t krylov_step(double* X, const KrylovBufs& b, const KrylovArgs& a0, int
             hipLaunchKernelGGL(k_kry_c, grid, blk, 0, st, X, b.R, b.RH, b.P[nxt], b.S, b.T,
                                b.partB, b.partC, b.sc, b.ndone, a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((it + 1) % poll_every == 0) {
+            if ((it + 1) % poll_every != 0) continue;
+            if (!piped) {
                 if ((e = hipMemcpyAsync(&nd, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st)) !=
                     hipSuccess)
                     return e;
                 if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
                 if (nd >= a.count) { ++it; break; }
+                continue;
             }
+            const int slot = polls & 1;
+            hipEvent_t ev = static_cast<hipEvent_t>(b.pev[slot]);
+            if ((e = hipMemcpyAsync(b.hpoll + slot, b.ndone, sizeof(int), hipMemcpyDeviceToHost,
+                                    st)) != hipSuccess)
+                return e;
+            if ((e = hipEventRecord(ev, st)) != hipSuccess) return e;
+            ++polls;
+            if (pending >= 0) {
+                if ((e = hipEventSynchronize(static_cast<hipEvent_t>(b.pev[pending]))) != hipSuccess)
+                    return e;
+                if (b.hpoll[pending] >= a.count) {
+                    idle += it + 1 - pending_it;   // the round queued after that poll
+                    ++it;
+                    break;
+                }
+            }
+            pending = slot;
+            pending_it = it + 1;
         }
+        pending = -1;
         // true residuals of the finished slices; restarted ones continue
         hipLaunchKernelGGL(k_kry_check, grid, blk, 0, st, X, b.B, b.R, b.RH, b.P[it & 1],
                            b.V[it & 1], b.partC, b.sc, a);
@@ -492,7 +520,7 @@ hipError_t krylov_step(double* X, const KrylovBufs& b, const KrylovArgs& a0, int
     if ((e = hipMemcpyAsync(&nd, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     *host_done = nd;
-    *iters_out = it;
+    *iters_out = it - idle;
     return hipGetLastError();
 }
 

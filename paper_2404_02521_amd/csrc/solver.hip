@@ -274,6 +274,8 @@ struct pr_solver {
     bool weights_ready = false;        // row-weight table of the step kernel written
     bool implicit = false;             // PR_FINE_IMPLICIT
     bool implicit_g = false;           // PR_G_IMPLICIT
+    int* kry_pin = nullptr;            // BiCGStab: 2 pinned slots for the finished-slice count
+    hipEvent_t kry_ev[2]{};            // ... and their events (polls read one round late)
     int64_t kry_iters = 0;             // BiCGStab iterations of this call (summed over steps)
     int kry_max = 0;                   // most iterations of one step
     int kry_unconv = 0;                // slice-steps that stopped unconverged
@@ -383,6 +385,9 @@ pr_status implicit_sweep(pr_solver* s, const double* Ubase, int first, int count
     b.partC = s->at<double>(s->L.kpC);
     b.sc = s->at<KScal>(s->L.ksc);
     b.ndone = s->at<int>(s->L.kdone);
+    b.hpoll = s->kry_pin;
+    b.pev[0] = s->kry_ev[0];
+    b.pev[1] = s->kry_ev[1];
     KrylovArgs a{};
     a.g = g;
     a.c = s->coef;
@@ -1509,6 +1514,19 @@ pr_status setup_solver(pr_solver* s, const pr_grid* grid, const pr_model* model,
             eok = eok && hipEventCreateWithFlags(&s->pipe_ev[i], hipEventDisableTiming) == hipSuccess;
         s->pipe = eok;   // otherwise the chain stays serial (the objects are released later)
     }
+    if (s->implicit || s->implicit_g) {
+        // pinned slots and events for the pipelined convergence polls of BiCGStab;
+        // without them the polls wait for the stream (same results)
+        bool kok = hipHostMalloc(reinterpret_cast<void**>(&s->kry_pin), 2 * sizeof(int)) ==
+                   hipSuccess;
+        if (!kok) s->kry_pin = nullptr;
+        for (auto& e : s->kry_ev)
+            kok = kok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (!kok && s->kry_pin) {
+            (void)hipHostFree(s->kry_pin);
+            s->kry_pin = nullptr;
+        }
+    }
     if ((opt->flags & PR_FLAG_TIME_STEPS) && !s->graph) {
         s->step_ev.resize(2 * (size_t)mf, nullptr);
         for (auto& e : s->step_ev)
@@ -1536,6 +1554,9 @@ void release_runtime_objects(pr_solver* s) {
     for (auto& e : s->pipe_ev)
         if (e) (void)hipEventDestroy(e);
     if (s->chain_stream) (void)hipStreamDestroy(s->chain_stream);
+    for (auto& e : s->kry_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->kry_pin) (void)hipHostFree(s->kry_pin);
 }
 
 // ---------------------------------------------------------------------------
