@@ -49,6 +49,11 @@ def test_alone_vs_mix(pr, ragged):
         assert infos[rid]["iters"] == alone.iters
         assert np.array_equal(host(sv.result(rid)), host(alone.value)), (inst.M, k)
     assert sv.peaks()[0] <= 4
+    st = sv.ragged_stats()
+    if ragged:
+        assert st["launches"] >= 1 and st["entries"] >= st["launches"]
+    else:
+        assert st == {"ticks": 0, "launches": 0, "entries": 0}
     sv.close()
 
 
