@@ -97,13 +97,14 @@ enum { PR_G_NUMERICAL = 0, /* explicit Euler on a coarse grid, injection + bilin
                               (default 1), each solved by the BiCGStab of PR_FINE_IMPLICIT
                               (krylov_tol, krylov_max_iters); needs PR_FP64 */ };
 
-/* Option flags.  PR_FLAG_TIME_STEPS: bracket every 8th explicit fine-step
- * launch of each sweep (the first included) with HIP events on the solver's
- * stream and report their summed durations in pr_stats.t_step_kernels_ms, their
- * number and algorithmic bytes in timed_step_launches / timed_step_bytes
- * (without the flag the field brackets the whole run of step launches, gaps
- * included).  The launches of one sweep all have the same shape, so the sample
- * gives their average duration at an eighth of the event cost. */
+/* Option flags.  PR_FLAG_TIME_STEPS: bracket runs of 8 consecutive explicit
+ * fine-step launches (a run also ends with its sweep) with HIP events on the
+ * solver's stream and report their summed durations in
+ * pr_stats.t_step_kernels_ms, the launches and their algorithmic bytes in
+ * timed_step_launches / timed_step_bytes (without the flag the field brackets
+ * the whole run of step launches, gaps included).  A run's duration over its
+ * launches is their launch-to-launch time: the dispatch delay of a run's first
+ * launch is spread over the run. */
 #define PR_FLAG_TIME_STEPS 1u
 /* PR_FLAG_GRAPH: capture the initial sweep and each Parareal iteration k (its
  * fine sweep, coarse chain, correction and norm) into a HIP graph once, on a

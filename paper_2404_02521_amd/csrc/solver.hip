@@ -284,7 +284,7 @@ struct pr_solver {
     int step_fit = 1;                  // PR_STEP_FIT: at most wave_target wavefronts per launch
     std::map<int, int64_t> graph_launches;   // step launches captured in graph k
     std::map<int, double> graph_bytes;
-    int ev_every = 8;                  // PR_FLAG_TIME_STEPS: time every ev_every-th launch
+    int ev_every = 8;                  // PR_FLAG_TIME_STEPS: step launches per timed run
     int64_t timed_launches = 0;        // launches bracketed by events in this call
     double timed_bytes = 0;            // their algorithmic bytes
     int64_t sweep_launches = 0;        // step launches of the last fine_sweep
@@ -452,6 +452,35 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         HIPCHK(hipStreamIsCapturing(s->stream, &cs));
         if (cs == hipStreamCaptureStatusNone) s->weights_ready = true;
     }
+    // PR_FLAG_TIME_STEPS: runs of ev_every consecutive step launches (a run also
+    // ends with the sweep) are bracketed by events; a run's elapsed time over its
+    // launches is their launch-to-launch duration, the first launch's dispatch
+    // delay spread over the run
+    struct RunTimer {
+        pr_solver* s;
+        bool on;
+        int n = 0;
+        double bytes = 0;
+        bool open = false;
+        hipError_t begin() {
+            if (!on || open || s->step_ev_used + 2 > (int)s->step_ev.size()) return hipSuccess;
+            open = true;
+            n = 0;
+            bytes = 0;
+            return hipEventRecord(s->step_ev[s->step_ev_used], s->stream);
+        }
+        hipError_t end(double b, bool last) {
+            if (!open) return hipSuccess;
+            n += 1;
+            bytes += b;
+            if (n < s->ev_every && !last) return hipSuccess;
+            open = false;
+            s->step_ev_used += 2;
+            s->timed_launches += n;
+            s->timed_bytes += bytes;
+            return hipEventRecord(s->step_ev[s->step_ev_used - 1], s->stream);
+        }
+    } rt{s, step_ms != nullptr};
     if (s->fp32) {
         float* A = s->at<float>(tmp ? s->L.tA : s->L.dA) + off;
         float* B = s->at<float>(tmp ? s->L.tB : s->L.dB) + off;
@@ -462,17 +491,10 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         for (int q = 1; q < s->mF;) {
             const int S = std::min(fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
-            const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
-                            s->step_ev_used + 2 <= (int)s->step_ev.size();
-            if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
+            HIPCHK(rt.begin());
             HIPCHK(launch_fine_tb_f32(A, Lb, B, s->at<float>(s->L.wt), b, S, s->stream));
             const double bytes = 12.0 * S * (double)count * g.nin * g.nin;
-            if (tv) {
-                HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
-                s->step_ev_used += 2;
-                s->timed_launches += 1;
-                s->timed_bytes += bytes;
-            }
+            HIPCHK(rt.end(bytes, q + S >= s->mF));
             s->sweep_launches += 1;
             s->sweep_bytes += bytes;
             std::swap(A, B);
@@ -487,18 +509,11 @@ pr_status fine_sweep(pr_solver* s, const double* Ubase, int first, int count, bo
         for (int q = 0; q < s->mF;) {
             const int S = std::min(fuse, s->mF - q);
             StepArgs b = tb_args(s, g, s->dtF, first, count, q, S);
-            const bool tv = step_ms && s->sweep_launches % s->ev_every == 0 &&
-                            s->step_ev_used + 2 <= (int)s->step_ev.size();
-            if (tv) HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used], s->stream));
+            HIPCHK(rt.begin());
             HIPCHK(launch_fine_tb_f64(q == 0 ? Ubase + (long long)first * g.stride : A,
                                       q == 0 ? A : B, s->at<double>(s->L.wt), b, S, s->stream));
             const double bytes = 16.0 * S * (double)count * g.nin * g.nin;
-            if (tv) {
-                HIPCHK(hipEventRecord(s->step_ev[s->step_ev_used + 1], s->stream));
-                s->step_ev_used += 2;
-                s->timed_launches += 1;
-                s->timed_bytes += bytes;
-            }
+            HIPCHK(rt.end(bytes, q + S >= s->mF));
             s->sweep_launches += 1;
             s->sweep_bytes += bytes;
             if (q > 0) std::swap(A, B);
