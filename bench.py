@@ -13,8 +13,8 @@ outside the timed region.
 
 Prints ONE JSON line: solves/s (value), per-solve latency p50/p99, the
 roofline of the dominant kernel (the FP32 explicit step) from HIP events
-around every 8th step launch of each sweep, and the FP64 oracle timed on the
-host cores.
+around runs of 8 consecutive step launches (every launch of the timed solves),
+and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
