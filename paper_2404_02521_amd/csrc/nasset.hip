@@ -11,7 +11,7 @@
 //
 // Kernels:
 //   k3_step    : one explicit step of every active slice.  A workgroup owns a
-//                tile of 16 j-rows x 64 k-columns (two rows per thread) and
+//                tile of 16 j-rows x 64 k-columns (256 threads, four rows each) and
 //                marches along i over a chunk of planes through a ring of four
 //                LDS planes (the tile and its one-node halo): each plane is
 //                read from HBM once per tile and serves three output planes;
@@ -39,7 +39,7 @@
 namespace pr3 {
 
 constexpr int kTK = 64;                  // k columns per tile: one wavefront
-constexpr int kThreads = 512;            // per workgroup: kTK x (TJ / RJ)
+constexpr int kThreads = 512;            // workgroup of the 512-thread tile shapes: kTK x (TJ / RJ)
 constexpr int kSlots = 4;                // LDS ring of planes
 constexpr int kCorrBlock = 256;
 
@@ -80,15 +80,16 @@ struct Step3 {
 
 // TJ j-rows per tile, RJ rows per thread (rows tj, tj + TJ / RJ, ...).
 template <int TJ, int RJ>
-__global__ __launch_bounds__(kThreads) void k3_step(const double* __restrict__ in,
+__global__ __launch_bounds__(kTK * TJ / RJ) void k3_step(const double* __restrict__ in,
                                                     double* __restrict__ out, Step3 a) {
 #pragma clang fp contract(on)
-    static_assert(kTK * TJ / RJ == kThreads, "tile shape and workgroup size disagree");
+    constexpr int kNT = kTK * TJ / RJ;   // threads of the workgroup
+    static_assert(TJ % RJ == 0 && kNT <= 1024, "tile shape and workgroup size disagree");
     constexpr int kTJ = TJ, kRJ = RJ;
     // A tile and its one-node halo: (kTJ + 2) x (kTK + 2) values per plane, at
-    // most kPer per thread (element e = threadIdx.x + t * kThreads).
+    // most kPer per thread (element e = threadIdx.x + t * kNT).
     constexpr int kTile = (kTJ + 2) * (kTK + 2);
-    constexpr int kPer = (kTile + kThreads - 1) / kThreads;
+    constexpr int kPer = (kTile + kNT - 1) / kNT;
     __shared__ double pl[kSlots][kTJ + 2][kTK + 2];
     const G3& g = a.g;
     const int tk = threadIdx.x % kTK, tj = threadIdx.x / kTK;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k3_step(const double* __restrict__ i
     bool eon[kPer], ein[kPer];
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
-        const int e = threadIdx.x + t * kThreads;
+        const int e = threadIdx.x + t * kNT;
         ej[t] = jb + e / (kTK + 2);
         ek[t] = kb + e % (kTK + 2);
         eon[t] = e < kTile && ej[t] < g.n && ek[t] < g.n;   // past the grid: never read
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void k3_step(const double* __restrict__ i
         double* slot = &pl[i & (kSlots - 1)][0][0];
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
-            const int e = threadIdx.x + t * kThreads;
+            const int e = threadIdx.x + t * kNT;
             if (e < kTile) slot[e] = r[t];
         }
     };
@@ -411,6 +412,8 @@ struct pr3_solver {
     bool events = false;
     int tile_rows = 16;   // j-rows per step tile: 8, 16 or 32 (PR3_TILE_ROWS)
     int xcd = 1;          // XCD-aware workgroup order of the step kernel (PR3_XCD; 0: off)
+    bool half_wg = true;  // 8- and 16-row tiles on 256 threads, twice the rows per thread
+                          // (PR3_HALF_WG=0: on 512 threads)
     std::string err;
     template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
 };
@@ -459,8 +462,12 @@ pr_status sweep(pr3_solver* s, const G3& g, const C3& c, const B3& b, const doub
         a.tq = q * dt;
         if (TJ == 32)
             hipLaunchKernelGGL((k3_step<32, 4>), grid, dim3(kThreads), 0, s->st, src, dst, a);
+        else if (TJ == 8 && s->half_wg)
+            hipLaunchKernelGGL((k3_step<8, 2>), grid, dim3(kThreads / 2), 0, s->st, src, dst, a);
         else if (TJ == 8)
             hipLaunchKernelGGL((k3_step<8, 1>), grid, dim3(kThreads), 0, s->st, src, dst, a);
+        else if (s->half_wg)
+            hipLaunchKernelGGL((k3_step<16, 4>), grid, dim3(kThreads / 2), 0, s->st, src, dst, a);
         else
             hipLaunchKernelGGL((k3_step<16, 2>), grid, dim3(kThreads), 0, s->st, src, dst, a);
         P3CHK(hipGetLastError());
@@ -669,6 +676,7 @@ pr_status pr3_create(const pr3_problem* p, void* workspace, uint64_t workspace_b
         s->tile_rows = (t == 8 || t == 32) ? t : 16;
     }
     if (const char* e = std::getenv("PR3_XCD")) s->xcd = std::atoi(e) != 0;
+    if (const char* e = std::getenv("PR3_HALF_WG")) s->half_wg = std::atoi(e) != 0;
     bool ok = true;
     for (auto& e : s->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
     s->events = ok;
