@@ -46,9 +46,11 @@ __device__ __attribute__((always_inline)) inline void static_for(Fn&& f) {
 //        + wL_j u_{j-1} + gI_i j (mixed four-corner difference),
 // cR = 1 - dt (2 alpha_i + r), wP/wM = dt (alpha_i +- mu_i), gI = dt rho s1 s2 i / 4
 // per row (from this wavefront's LDS copy of the table `wt`), b2 = 2 dt beta_j,
-// wR/wL = dt (beta_j +- nu_j) per column (registers).  The j +- 1 neighbours
-// enter as DPP operands of the multiply-adds, so a point-step is eleven vector
-// operations.  Every row path evaluates the same expressions in the same order.
+// wR/wL = dt (beta_j +- nu_j) per column (registers).  The j +- 1 terms are
+// summed on the neighbour's lane (vr = wR_{j-1} u + gI (j-1) (u_{i+1} - u_{i-1})
+// and vl likewise) and enter as the DPP operands of the last two additions,
+// so a point-step is ten vector operations plus the per-row products.  Every
+// row path evaluates the same expressions in the same order.
 // ---------------------------------------------------------------------------
 // Longest row chunk of the temporally blocked kernel and the rows of its
 // per-wavefront weight table (chunk + 3 S + 1 for S <= 8).
@@ -143,10 +145,18 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
     const bool ring_lane = jl == jring;   // P_MID: this lane is the ring column
     const int rlane = rc_right ? RS : 0;    // P_MID: first ring lane of that column
 
-    // column weights (FP64, then rounded once)
-    const T fj = (T)jl;
-    const double Bj = a.c.a2 * (double)jl * (double)jl, Nj = a.c.hr * (double)jl;
-    const T wR = (T)(a.dt * (Bj + Nj)), wL = (T)(a.dt * (Bj - Nj)), b2 = (T)(2.0 * a.dt * Bj);
+    // column weights (FP64, then rounded once).  The j +- 1 terms are formed
+    // on the neighbour's lane and shifted once: lane k holds the weights of
+    // columns k - 1 (the right-hand term of that column) and k + 1 (its
+    // left-hand term), so wR_j u_{j+1} = shl1(wRs u)_j and wL_j u_{j-1} =
+    // shr1(wLs u)_j, and likewise the mixed term with (j -+ 1) in place of j.
+    auto colw = [&](int jj, double sgn) -> T {
+        const double B = a.c.a2 * (double)jj * (double)jj, N = a.c.hr * (double)jj;
+        return (T)(a.dt * (B + sgn * N));
+    };
+    const T wRs = colw(jl - 1, 1.0), wLs = colw(jl + 1, -1.0);
+    const T b2 = (T)(2.0 * a.dt * (a.c.a2 * (double)jl * (double)jl));
+    const T fjm = (T)(jl - 1), fjp = (T)(jl + 1);
 
     // Window of level q (0..S-1): three rows in slots 0..2; with the row loop
     // unrolled by 3 the newest row of iteration x sits in slot x % 3, so
@@ -245,15 +255,16 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
             const W4 w = wrow[x - x0 + S - q];
             const T wP = w.x, wM = w.y, cR = w.z, gI = w.w;
             const T dd = up - um;
-            const T mix = shl1(dd) - shr1(dd);   // (r+ - l+) - (r- - l-)
-            const T G = gI * fj;
-            T acc = (MODE == MODE_INCR) ? cR * u0 + (T)lbw[q - 1] : cR * u0;
-            acc = acc - b2 * u0;
+            // right-hand and left-hand neighbour terms of the neighbouring
+            // columns (u_{i,j} and the mixed difference u_{i+1,j} - u_{i-1,j})
+            const T vr = wRs * u0 + (gI * fjm) * dd;
+            const T vl = wLs * u0 - (gI * fjp) * dd;
+            const T cc = cR - b2;
+            T acc = (MODE == MODE_INCR) ? cc * u0 + (T)lbw[q - 1] : cc * u0;
             acc = acc + wP * up;
             acc = acc + wM * um;
-            acc = acc + wR * shl1(u0);
-            acc = acc + wL * shr1(u0);
-            acc = acc + G * mix;
+            acc = acc + shl1(vr);
+            acc = acc + shr1(vl);
             T c = acc;
             if (PATH == P_MID) {
                 const T rvq = mid_ring(q);
