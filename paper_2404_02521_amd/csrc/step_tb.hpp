@@ -211,8 +211,10 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
         constexpr int K2 = (K + 1) % 3;   // row before that
         const T cur_raw = pq[KP];
         const float cur_lb = lq[KP];
-        pq[KP] = raw(x + PF);
-        lq[KP] = rawlb(x + PF - 1);
+        if (PATH == P_GEN) {   // the unrolled paths refill the queue per PF rows
+            pq[KP] = raw(x + PF);
+            lq[KP] = rawlb(x + PF - 1);
+        }
         if (MODE == MODE_INCR) {
 #pragma unroll
             for (int q = S - 1; q > 0; --q) lbw[q] = lbw[q - 1];
@@ -298,17 +300,31 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
     const int fe = interior ? min(x1, M - 2) : x1;
     int x = x0;
     while (x <= x1 && (x < fb || x % PF != 0)) general(x++);
-    if (n_rc == 0) {
-        for (; x + PF - 1 <= fe; x += PF)
-            static_for<PF>([&](auto Kc) {
-                iter(Kc, std::integral_constant<int, P_FAST>{}, x + decltype(Kc)::value);
-            });
-    } else {
-        for (; x + PF - 1 <= fe; x += PF)
-            static_for<PF>([&](auto Kc) {
-                iter(Kc, std::integral_constant<int, P_MID>{}, x + decltype(Kc)::value);
-            });
-    }
+    // The unrolled paths issue the loads of the next PF rows at the top of
+    // the PF rows they evaluate and move them into the queue at the bottom:
+    // the move at the loop's back edge then waits on loads issued PF rows
+    // earlier, not on loads just issued.
+    auto unrolled = [&](auto Pc) __attribute__((always_inline)) {
+        for (; x + PF - 1 <= fe; x += PF) {
+            T pn[PF];
+            float ln[PF];
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                pn[k] = raw(x + PF + k);
+                ln[k] = rawlb(x + PF + k - 1);
+            }
+            static_for<PF>([&](auto Kc) { iter(Kc, Pc, x + decltype(Kc)::value); });
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                pq[k] = pn[k];
+                lq[k] = ln[k];
+            }
+        }
+    };
+    if (n_rc == 0)
+        unrolled(std::integral_constant<int, P_FAST>{});
+    else
+        unrolled(std::integral_constant<int, P_MID>{});
     while (x <= x1) general(x++);
 }
 
