@@ -109,6 +109,31 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
         const int rr = min(max(x0 - S + e, 0), M - 1);
         wrow[e] = *reinterpret_cast<const W4*>(wt + 4 * rr);
     }
+    // Row iterations of the unrolled paths: x in [S+1, M-2] for wavefronts
+    // with at most one ring column (P_MID also evaluates rows up to x + 2 <=
+    // M - 2).
+    const bool interior = n_rc <= 1;
+    const int fb = interior ? max(x0, S + 1) : x1 + 1;
+    const int fe = interior ? min(x1, M - 2) : x1;
+
+    // P_MID: the ring column's values for every iteration x in [fb, fe] and
+    // level q (0..S: row x - q at level q's time), in this wavefront's slice
+    // of LDS at entry (x - x0) (S + 1) + q, evaluated once by all lanes.
+    constexpr int RS = S + 1;
+    __shared__ T rtab[kBlock / kWave][kTbWRows * RS];
+    T* rring = rtab[threadIdx.x >> 6];
+    if (n_rc == 1 && fb <= fe) {
+        const double yr = jring * a.bc.h;
+        const int nv = (fe - fb + 1) * RS;
+        for (int e = lane; e < nv; e += kWave) {
+            const int x = fb + e / RS, q = e % RS;
+            const double tq = Tn + (a.step + q) * a.dt;
+            const double xr = (x - q) * a.bc.h;
+            double v = ring_value<CHEAP>(a.bc, xr, yr, tq, exp(-a.bc.r * tq));
+            if (MODE == MODE_INCR) v -= ring_value<CHEAP>(a.bc, xr, yr, Tn, disc_T);
+            rring[(x - x0) * RS + q] = (T)v;
+        }
+    }
     // the LDS writes of this wavefront complete before its reads below
     __builtin_amdgcn_s_waitcnt(0xC07F);
 
@@ -125,10 +150,9 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
     // level q needs the ring value at row x - q.  One pass over the lanes
     // evaluates them for three consecutive newest rows x + k (k = 0..2), both
     // ring columns c and every level q: lane RS (2k + c) + q holds column c
-    // (0: column 0, 1: column M-1), level q, row x + k - q, and the levels
-    // pick their values up with readlane.  The values are the same
-    // expressions as ring(x + k - q, q).
-    constexpr int RS = S + 1;
+    // (0: column 0, 1: column M-1), level q, row x + k - q; P_GEN evaluates
+    // them per row and its levels pick up the lanes with k = 0 by readlane.
+    // The values are the same expressions as ring(x + k - q, q).
     static_assert(6 * RS <= kWave, "ring lanes: 3 rows x 2 columns x (S + 1) levels");
     const int bl = min(lane, 6 * RS - 1);
     const int bq = bl % RS;
@@ -143,7 +167,6 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
         return (T)v;
     };
     const bool ring_lane = jl == jring;   // P_MID: this lane is the ring column
-    const int rlane = rc_right ? RS : 0;    // P_MID: first ring lane of that column
 
     // column weights (FP64, then rounded once).  The j +- 1 terms are formed
     // on the neighbour's lane and shifted once: lane k holds the weights of
@@ -200,9 +223,8 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
     //  P_FAST: every row touched (x-S .. x) is interior and no lane is on the
     //          ring, so no boundary logic is compiled in;
     //  P_MID : rows as for P_FAST, one ring column in the wavefront; its values
-    //          for rows x .. x+2 are evaluated when K = 0 (x % 3 == 0);
+    //          come from the wavefront's LDS table (one broadcast read each);
     //  P_GEN : anything (ring rows, rows outside the grid, both ring columns).
-    T rvb = T(0);   // ring values of the current three rows (P_MID)
     auto iter = [&](auto KPc, auto Pc, int x) __attribute__((always_inline)) {
         constexpr int KP = decltype(KPc)::value;
         constexpr int K = KP % 3;
@@ -222,15 +244,14 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
         }
         T rv = T(0);   // P_GEN: ring values of this row (lanes with k = 0)
         if (PATH == P_GEN && n_rc > 0) rv = ring_batch(x);
-        if (PATH == P_MID && K == 0) rvb = ring_batch(x);
         // value of the wavefront's ring column at level q (P_MID)
         auto mid_ring = [&](int q) __attribute__((always_inline)) -> T {
-            return bcast_u(rvb, rlane + RS * 2 * K + q);
+            return rring[(x - x0) * RS + q];
         };
         {
             T c = cur_raw;
-            // readlane is evaluated by the whole wavefront before the select:
-            // under a lane condition it would become a branch
+            // ring values are read by the whole wavefront before the select:
+            // under a lane condition the read would become a branch
             if (PATH == P_MID) {
                 const T rv0 = mid_ring(0);
                 c = ring_lane ? rv0 : c;
@@ -293,11 +314,6 @@ __device__ __attribute__((always_inline)) inline void tb_body(const T* __restric
             if (x % PF == decltype(Kc)::value) iter(Kc, std::integral_constant<int, P_GEN>{}, x);
         });
     };
-    // interior iterations: x in [S+1, M-2] for wavefronts with at most one
-    // ring column (P_MID also evaluates rows up to x + 2 <= M - 2)
-    const bool interior = n_rc <= 1;
-    const int fb = interior ? max(x0, S + 1) : x1 + 1;
-    const int fe = interior ? min(x1, M - 2) : x1;
     int x = x0;
     while (x <= x1 && (x < fb || x % PF != 0)) general(x++);
     // The unrolled paths issue the loads of the next PF rows at the top of
